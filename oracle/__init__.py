@@ -1,0 +1,144 @@
+"""Plain FP64 CPU oracle for the line-of-sight projection (test infrastructure).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never does, and the two
+share no code: the arithmetic lives in ``los_oracle.c`` (plain C, IEEE double,
+OpenMP over k), which this module compiles on demand with gcc and calls
+through ctypes.
+
+Functions follow the gCAMB paper, Sec. 2.1 Eq. 1-3 (C_l and the LOS transfer
+integrals) and Sec. 3.2 / Algorithm 1 (loop over k, then l, then tau):
+
+* :func:`sph_jl`        -- j_l(x), l = 0..lmax (spherical Bessel kernel, flat space)
+* :func:`bessel_table`  -- j_l(x_i) as an [l - lmin][i] table
+* :func:`project`       -- Delta^X_l(k_i) = sum_n w_n S_X(k_i, tau_n) j_l(k_i (tau0 - tau_n))
+* :func:`cl`            -- C^XY_l = 4 pi sum_i w_i P(k_i) Delta^X_l(k_i) Delta^Y_l(k_i)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "los_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liblos_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int32_p = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = False) -> str:
+    """Compile ``los_oracle.c`` into ``liblos_oracle.so`` (gcc -O2 -fopenmp, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-fno-fast-math",
+               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB_PATH)
+            lib.oracle_sph_jl.argtypes = [ctypes.c_int32, ctypes.c_double, _c_double_p]
+            lib.oracle_bessel_table.argtypes = [_c_double_p, ctypes.c_int64, ctypes.c_int32,
+                                                ctypes.c_int32, _c_double_p]
+            lib.oracle_project.argtypes = [
+                ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                _c_double_p, _c_double_p, _c_double_p, _c_double_p, ctypes.c_int32,
+                _c_double_p, _c_double_p]
+            lib.oracle_cl.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _c_double_p,
+                                      _c_double_p, _c_double_p, _c_int32_p, ctypes.c_int32,
+                                      _c_double_p]
+            lib.oracle_num_threads.argtypes = []
+            for f in (lib.oracle_sph_jl, lib.oracle_bessel_table, lib.oracle_project,
+                      lib.oracle_cl, lib.oracle_num_threads):
+                f.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_c_double_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s failed with status %d" % (what, rc))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses (``OMP_NUM_THREADS`` or all cores)."""
+    return int(_load().oracle_num_threads())
+
+
+def sph_jl(lmax: int, x: float) -> np.ndarray:
+    """j_l(x) for l = 0..lmax in FP64."""
+    out = np.empty(lmax + 1, dtype=np.float64)
+    _check(_load().oracle_sph_jl(int(lmax), float(x), out.ctypes.data_as(_c_double_p)), "sph_jl")
+    return out
+
+
+def bessel_table(x, lmin: int, lmax: int) -> np.ndarray:
+    """out[l - lmin, i] = j_l(x[i])."""
+    x, xp = _f64(x)
+    out = np.empty((lmax - lmin + 1, x.size), dtype=np.float64)
+    _check(_load().oracle_bessel_table(xp, x.size, int(lmin), int(lmax),
+                                       out.ctypes.data_as(_c_double_p)), "bessel_table")
+    return out
+
+
+def project(lmin, lmax, k, tau, tau0, w_tau, S, with_abs=False, k_range=None):
+    """LOS projection (Eq. 2-3).
+
+    ``S`` is [nsrc, nk, ntau]; returns delta [nk, nl, nsrc] (and the absolute
+    sum ``A`` of the same shape if ``with_abs``).  ``k_range=(a, b)`` computes
+    only rows a..b-1 and returns arrays of b - a rows (each row depends only on
+    its own k and S row, so this equals slicing the full result).
+    """
+    S = np.asarray(S)
+    k = np.asarray(k)
+    if k_range is not None:
+        a, b = k_range
+        k = k[a:b]
+        S = S[:, a:b, :]
+    k, kp = _f64(k)
+    tau, tp = _f64(tau)
+    w_tau, wp = _f64(w_tau)
+    S, sp = _f64(S)
+    nsrc, nk, ntau = S.shape
+    assert nk == k.size and ntau == tau.size == w_tau.size
+    nl = lmax - lmin + 1
+    delta = np.empty((nk, nl, nsrc))
+    absd = np.empty((nk, nl, nsrc)) if with_abs else None
+    rc = _load().oracle_project(
+        int(lmin), int(lmax), nk, ntau, float(tau0), kp, tp, wp, sp, nsrc,
+        delta.ctypes.data_as(_c_double_p),
+        absd.ctypes.data_as(_c_double_p) if with_abs else None)
+    _check(rc, "project")
+    return (delta, absd) if with_abs else delta
+
+
+def cl(delta, w_lnk, Pk, pairs) -> np.ndarray:
+    """C_l (Eq. 1): returns [npairs, nl] with cl[p, l] = 4 pi sum_k w P delta[k,l,a] delta[k,l,b]."""
+    delta, dp = _f64(delta)
+    nk, nl, nsrc = delta.shape
+    w_lnk, wp = _f64(w_lnk)
+    Pk, pp = _f64(Pk)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    out = np.empty((pr.shape[0], nl), dtype=np.float64)
+    rc = _load().oracle_cl(nl, nk, nsrc, dp, wp, pp, pr.ctypes.data_as(_c_int32_p), pr.shape[0],
+                           out.ctypes.data_as(_c_double_p))
+    _check(rc, "cl")
+    return out

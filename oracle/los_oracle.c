@@ -1,0 +1,269 @@
+/*
+ * Plain FP64 CPU oracle for the line-of-sight (LOS) projection and the
+ * angular power spectrum of a flat-space Einstein-Boltzmann solver.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file.  The GPU library shares
+ * no code, header or table with it.
+ *
+ * What it computes (gCAMB paper, Sec. 2.1 "Key equations", Eq. 1-3, and
+ * Sec. 3.2 with Algorithm 1):
+ *
+ *   chi_n          = tau0 - tau_n                      (comoving distance)
+ *   x_{i,n}        = k_i * chi_n
+ *   Delta^X_l(k_i) = sum_n w_n S_X(k_i, tau_n) j_l(x_{i,n})       (Eq. 2-3)
+ *   C^{XY}_l       = 4 pi sum_i w_i P(k_i) Delta^X_l(k_i) Delta^Y_l(k_i)
+ *                                                                  (Eq. 1)
+ *
+ * The radial kernel is the spherical Bessel function j_l for every source
+ * (flat space, Sec. 2.1 below Eq. 3).  w_n are the caller's tau-quadrature
+ * weights and w_i the caller's ln k quadrature weights (Eq. 1 integrates
+ * dk/k = d ln k).  No band cut: every tau contributes to every (l, k).
+ *
+ * j_l(x) is computed by one of two textbook methods, chosen by x:
+ *   x >= lmax + 1 : upward three-term recurrence from the closed forms
+ *                   j_0 = sin x / x, j_1 = sin x / x^2 - cos x / x
+ *                   (stable while l < x);
+ *   otherwise     : Miller's downward recurrence started far above the
+ *                   turning point, normalised with the sum rule
+ *                   sum_l (2l+1) j_l(x)^2 = 1;
+ *   x < 1e-150    : leading power-series terms (exact in FP64 there).
+ * All arithmetic is IEEE double, no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#if defined(__SSE2__)
+#include <xmmintrin.h>
+#endif
+
+#define OR_OK 0
+#define OR_ERR_INVALID 1
+#define OR_ERR_OOM 3
+
+static const double OR_PI = 3.14159265358979323846264338327950288;
+
+/* Subnormal results (|v| < 2.2e-308) are flushed to zero in every oracle
+ * thread: they cannot move any comparison made at the tolerances used, and
+ * x86 subnormal arithmetic is ~100x slower.  Everything else is plain IEEE. */
+static void flush_subnormals(void)
+{
+#if defined(__SSE2__)
+    _mm_setcsr(_mm_getcsr() | 0x8040); /* FTZ | DAZ */
+#endif
+}
+
+/* Upward recurrence j_{l+1} = (2l+1)/x j_l - j_{l-1}, valid for x >= lmax+1. */
+static void jl_upward(int32_t lmax, double x, double *out)
+{
+    double s = sin(x), c = cos(x);
+    out[0] = s / x;
+    if (lmax == 0)
+        return;
+    out[1] = s / (x * x) - c / x;
+    for (int32_t l = 1; l < lmax; ++l)
+        out[l + 1] = (2.0 * l + 1.0) / x * out[l] - out[l - 1];
+}
+
+/* Miller downward recurrence j_{l-1} = (2l+1)/x j_l - j_{l+1} from a start
+ * far above max(lmax, x), normalised by the sum rule.  The start value is
+ * positive and j_l(x) > 0 for l > x, so the sequence carries the right sign.
+ * Whenever the running value grows past 2^100 the two live values and the
+ * running sum are brought back near 1 by an exact power-of-two scaling; each
+ * stored value remembers the total scaling in force when it was stored
+ * (ex[l]), and all stored values are brought to the final scaling at the end. */
+static void jl_miller(int32_t lmax, double x, double *out, int *ex)
+{
+    double xm = x > 1.0 ? x : 1.0;
+    int32_t top = lmax > (int32_t)ceil(x) ? lmax : (int32_t)ceil(x);
+    int32_t ls = top + (int32_t)ceil(20.0 * cbrt(xm / 2.0)) + 20;
+    double jp = 0.0;   /* j~_{l+1} */
+    double jc = 1.0;   /* j~_l     */
+    double sum = (2.0 * ls + 1.0) * jc * jc;
+    int e_tot = 0;     /* values are currently multiplied by 2^-e_tot */
+    for (int32_t l = ls; l >= 1; --l) {
+        double jn = (2.0 * l + 1.0) / x * jc - jp; /* j~_{l-1} */
+        jp = jc;
+        jc = jn;
+        sum += (2.0 * (l - 1) + 1.0) * jc * jc;
+        if (l - 1 <= lmax) {
+            out[l - 1] = jc;
+            ex[l - 1] = e_tot;
+        }
+        if (fabs(jc) > 0x1p100) {
+            int e = ilogb(jc);
+            jc = ldexp(jc, -e);
+            jp = ldexp(jp, -e);
+            sum = ldexp(sum, -2 * e);
+            e_tot += e;
+        }
+    }
+    double norm = sqrt(sum);
+    for (int32_t l = 0; l <= lmax; ++l)
+        out[l] = ldexp(out[l], ex[l] - e_tot) / norm;
+}
+
+/* j_l(x) for l = 0..lmax, x >= 0, into out[0..lmax]. */
+int oracle_sph_jl(int32_t lmax, double x, double *out)
+{
+    flush_subnormals();
+    if (lmax < 0 || !(x >= 0.0) || !isfinite(x) || out == NULL)
+        return OR_ERR_INVALID;
+    if (x < 1e-150) {
+        /* power series: j_l(x) = x^l / (2l+1)!! (1 - O(x^2)) */
+        for (int32_t l = 0; l <= lmax; ++l)
+            out[l] = 0.0;
+        out[0] = 1.0;
+        if (lmax >= 1)
+            out[1] = x / 3.0;
+        if (lmax >= 2)
+            out[2] = x * x / 15.0;
+        return OR_OK;
+    }
+    if (x >= (double)lmax + 1.0) {
+        jl_upward(lmax, x, out);
+        return OR_OK;
+    }
+    int *ex = (int *)malloc(sizeof(int) * (size_t)(lmax + 1));
+    if (ex == NULL)
+        return OR_ERR_OOM;
+    jl_miller(lmax, x, out, ex);
+    free(ex);
+    return OR_OK;
+}
+
+/* Table form: out[(l - lmin) * nx + i] = j_l(x[i]), l = lmin..lmax. */
+int oracle_bessel_table(const double *x, int64_t nx, int32_t lmin, int32_t lmax, double *out)
+{
+    if (x == NULL || out == NULL || nx < 0 || lmin < 0 || lmax < lmin)
+        return OR_ERR_INVALID;
+    int bad = 0;
+#pragma omp parallel
+    {
+        flush_subnormals();
+        double *jl = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        if (jl == NULL) {
+#pragma omp atomic write
+            bad = OR_ERR_OOM;
+        }
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nx; ++i) {
+            if (jl == NULL)
+                continue;
+            if (oracle_sph_jl(lmax, x[i], jl) != OR_OK) {
+#pragma omp atomic write
+                bad = OR_ERR_INVALID;
+                continue;
+            }
+            for (int32_t l = lmin; l <= lmax; ++l)
+                out[(int64_t)(l - lmin) * nx + i] = jl[l];
+        }
+        free(jl);
+    }
+    return bad;
+}
+
+/*
+ * Eq. 2-3: delta[(i*nl + (l-lmin))*nsrc + s] = sum_n w_tau[n] S[s][i][n] j_l(k_i (tau0 - tau_n))
+ * S is [nsrc][nk][ntau] row-major.  If absdelta is not NULL it receives
+ * sum_n |w_tau[n] S[s][i][n] j_l(x)| in the same layout (the scale used for
+ * normwise comparisons).
+ */
+int oracle_project(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
+                   const double *k, const double *tau, const double *w_tau, const double *S,
+                   int32_t nsrc, double *delta, double *absdelta)
+{
+    if (lmin < 0 || lmax < lmin || nk < 0 || ntau < 0 || nsrc < 1 || k == NULL || tau == NULL ||
+        w_tau == NULL || S == NULL || delta == NULL)
+        return OR_ERR_INVALID;
+    const int64_t nl = (int64_t)lmax - lmin + 1;
+    int bad = 0;
+#pragma omp parallel
+    {
+        flush_subnormals();
+        double *jl = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        if (jl == NULL) {
+#pragma omp atomic write
+            bad = OR_ERR_OOM;
+        }
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nk; ++i) {
+            if (jl == NULL)
+                continue;
+            double *d = delta + i * nl * nsrc;
+            double *a = absdelta ? absdelta + i * nl * nsrc : NULL;
+            for (int64_t q = 0; q < nl * nsrc; ++q) {
+                d[q] = 0.0;
+                if (a)
+                    a[q] = 0.0;
+            }
+            for (int64_t n = 0; n < ntau; ++n) {
+                double chi = tau0 - tau[n];
+                double x = k[i] * chi;
+                if (oracle_sph_jl(lmax, x, jl) != OR_OK) {
+#pragma omp atomic write
+                    bad = OR_ERR_INVALID;
+                    continue;
+                }
+                for (int32_t s = 0; s < nsrc; ++s) {
+                    double ws = w_tau[n] * S[((int64_t)s * nk + i) * ntau + n];
+                    if (ws == 0.0)
+                        continue; /* adds exactly zero */
+                    for (int32_t l = lmin; l <= lmax; ++l) {
+                        double term = ws * jl[l];
+                        d[(int64_t)(l - lmin) * nsrc + s] += term;
+                        if (a)
+                            a[(int64_t)(l - lmin) * nsrc + s] += fabs(term);
+                    }
+                }
+            }
+        }
+        free(jl);
+    }
+    return bad;
+}
+
+/*
+ * Eq. 1 with the ln k quadrature written out:
+ *   cl[p*nl + l] = 4 pi sum_i w_lnk[i] Pk[i] delta[i][l][a_p] delta[i][l][b_p]
+ * pairs = {a_0, b_0, a_1, b_1, ...} are source indices into delta's last axis.
+ */
+int oracle_cl(int32_t nl, int64_t nk, int32_t nsrc, const double *delta, const double *w_lnk,
+              const double *Pk, const int32_t *pairs, int32_t npairs, double *cl)
+{
+    if (nl < 1 || nk < 0 || nsrc < 1 || delta == NULL || w_lnk == NULL || Pk == NULL ||
+        pairs == NULL || npairs < 1 || cl == NULL)
+        return OR_ERR_INVALID;
+    for (int32_t p = 0; p < npairs; ++p)
+        if (pairs[2 * p] < 0 || pairs[2 * p] >= nsrc || pairs[2 * p + 1] < 0 ||
+            pairs[2 * p + 1] >= nsrc)
+            return OR_ERR_INVALID;
+#pragma omp parallel
+    flush_subnormals();
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int32_t p = 0; p < npairs; ++p) {
+        for (int32_t l = 0; l < nl; ++l) {
+            int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
+            double acc = 0.0;
+            for (int64_t i = 0; i < nk; ++i) {
+                const double *d = delta + ((int64_t)i * nl + l) * nsrc;
+                acc += w_lnk[i] * Pk[i] * d[a] * d[b];
+            }
+            cl[(int64_t)p * nl + l] = 4.0 * OR_PI * acc;
+        }
+    }
+    return OR_OK;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

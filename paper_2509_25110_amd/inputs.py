@@ -1,0 +1,205 @@
+"""Seeded synthetic workloads for the line-of-sight projection.
+
+This module builds inputs only: the k and tau grids, their quadrature weights,
+the primordial spectrum P(k) and synthetic source functions S_X(k, tau).  It
+holds none of the projection arithmetic (no Bessel functions, no sums over
+tau or k), so the GPU path and the CPU oracle can both be fed from it.
+
+The paper's own workload (CAMB with Planck-2018 parameters, Sec. 3.1 and
+Table 1) needs the full Boltzmann hierarchy to produce source functions; these
+synthetic sources stand in for it with the same structure: a visibility-like
+peak near recombination, a late broad ISW-like term, an E source carrying k^2,
+and a broad lensing kernel.
+
+Grids (both ends included):
+* tau_n = n * tau0 / (ntau - 1), n = 0..ntau-1, tau0 = 14000 Mpc
+* k_i log-spaced on [kmin, kmax]
+* w_tau: trapezoid weights in tau; w_lnk: trapezoid weights in ln k
+* P(k) = A_s (k / 0.05)^(n_s - 1)
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+TAU0 = 14000.0
+K_PIVOT = 0.05
+PAIRS_TT = ((0, 0),)
+PAIRS_4 = ((0, 0), (1, 1), (0, 1), (2, 2))  # TT, EE, TE, phi-phi
+PAIR_NAMES_4 = ("TT", "EE", "TE", "PP")
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    lmin: int
+    lmax: int
+    k: np.ndarray          # [nk]
+    tau: np.ndarray        # [ntau]
+    tau0: float
+    w_tau: np.ndarray      # [ntau]
+    w_lnk: np.ndarray      # [nk]
+    Pk: np.ndarray         # [nk]
+    S: np.ndarray          # [nsrc, nk, ntau] float64
+    pairs: Tuple[Tuple[int, int], ...]
+    pair_names: Tuple[str, ...]
+    params: Dict[str, float] = dataclasses.field(default_factory=dict)
+
+    @property
+    def nk(self) -> int:
+        return int(self.k.size)
+
+    @property
+    def ntau(self) -> int:
+        return int(self.tau.size)
+
+    @property
+    def nl(self) -> int:
+        return self.lmax - self.lmin + 1
+
+    @property
+    def nsrc(self) -> int:
+        return int(self.S.shape[0])
+
+
+def tau_grid(ntau: int, tau0: float = TAU0) -> np.ndarray:
+    """Uniform tau nodes on [0, tau0]; the last node is exactly tau0 (so chi = 0 there)."""
+    return np.linspace(0.0, tau0, ntau)
+
+
+def log_k_grid(nk: int, kmin: float, kmax: float) -> np.ndarray:
+    return np.exp(np.linspace(np.log(kmin), np.log(kmax), nk))
+
+
+def trapezoid_weights(nodes: np.ndarray) -> np.ndarray:
+    """Trapezoid weights on (possibly non-uniform) nodes: w_0 = h_0/2, w_n = (h_{n-1}+h_n)/2."""
+    h = np.diff(nodes)
+    w = np.zeros_like(nodes)
+    w[:-1] += 0.5 * h
+    w[1:] += 0.5 * h
+    return w
+
+
+def primordial(k: np.ndarray, A_s: float, n_s: float) -> np.ndarray:
+    return A_s * (k / K_PIVOT) ** (n_s - 1.0)
+
+
+def gauss(tau: np.ndarray, mu: float, sig: float) -> np.ndarray:
+    return np.exp(-((tau - mu) ** 2) / (2.0 * sig * sig))
+
+
+def lensing_kernel(tau: np.ndarray) -> np.ndarray:
+    """Broad kernel sin^2(pi (tau - 2000) / 11500) on [2000, 13500], zero elsewhere."""
+    inside = (tau >= 2000.0) & (tau <= 13500.0)
+    return np.where(inside, np.sin(np.pi * (tau - 2000.0) / 11500.0) ** 2, 0.0)
+
+
+def sources(k: np.ndarray, tau: np.ndarray, nsrc: int, tau_star=280.0, width=20.0, a_isw=0.1):
+    """Synthetic S[src, k, tau]: T, then E = 0.5 k^2 g(tau), then the lensing kernel."""
+    g = gauss(tau, tau_star, width)[None, :]
+    kk = k[:, None]
+    S = np.empty((nsrc, k.size, tau.size), dtype=np.float64)
+    S[0] = g * (1.0 + 0.3 * np.cos(150.0 * kk)) + a_isw * gauss(tau, 12000.0, 1500.0)[None, :]
+    if nsrc > 1:
+        S[1] = 0.5 * kk * kk * g
+    if nsrc > 2:
+        S[2] = np.broadcast_to(lensing_kernel(tau)[None, :], (k.size, tau.size))
+    return S
+
+
+def _make(name, lmax, nk, kmax, ntau, nsrc, kmin=1e-4, A_s=2.1e-9, n_s=0.965, **src_kw):
+    k = log_k_grid(nk, kmin, kmax)
+    tau = tau_grid(ntau)
+    pairs = PAIRS_TT if nsrc == 1 else PAIRS_4
+    names = ("TT",) if nsrc == 1 else PAIR_NAMES_4
+    return Workload(name=name, lmin=2, lmax=lmax, k=k, tau=tau, tau0=TAU0,
+                    w_tau=trapezoid_weights(tau), w_lnk=trapezoid_weights(np.log(k)),
+                    Pk=primordial(k, A_s, n_s), S=sources(k, tau, nsrc, **src_kw),
+                    pairs=pairs, pair_names=names, params=dict(A_s=A_s, n_s=n_s, **src_kw))
+
+
+# The five benchmark configurations (the first three are single-model solves).
+CONFIGS = {
+    # plain FP64, one model, temperature only
+    "C1": dict(lmax=300, nk=400, kmax=0.05, ntau=600, nsrc=1),
+    # plain FP64 high accuracy, T/E/lensing
+    "C2": dict(lmax=2500, nk=4000, kmax=0.5, ntau=3000, nsrc=3),
+    # mixed-precision case
+    "C3": dict(lmax=5000, nk=8000, kmax=1.0, ntau=4000, nsrc=3),
+}
+
+DESCRIPTIONS = {
+    "C1": "TT, l=2..300, 400 log-k on [1e-4,0.05], 600 tau on [0,14000]",
+    "C2": "TT/EE/TE/PP, l=2..2500, 4000 log-k on [1e-4,0.5], 3000 tau on [0,14000]",
+    "C3": "TT/EE/TE/PP, l=2..5000, 8000 log-k on [1e-4,1.0], 4000 tau on [0,14000]",
+}
+
+
+def config(name: str) -> Workload:
+    c = CONFIGS[name]
+    return _make(name, **c)
+
+
+def small(lmax=40, nk=24, kmax=0.02, ntau=200, nsrc=3, kmin=1e-4, **kw) -> Workload:
+    """A small workload of the same structure (for quick parity tests)."""
+    return _make("small", lmax=lmax, nk=nk, kmax=kmax, ntau=ntau, nsrc=nsrc, kmin=kmin, **kw)
+
+
+# --- batched configuration: per-model parameter draws -------------------------------------
+
+BATCH_SEED = 20250925
+MASTER_NK = 8000
+MASTER_KMAX = 1.0
+
+
+@dataclasses.dataclass
+class ModelDraw:
+    lmax: int
+    nk: int
+    tau_star: float
+    width: float
+    a_isw: float
+    n_s: float
+    ln1e10As: float
+
+    @property
+    def A_s(self) -> float:
+        return float(np.exp(self.ln1e10As) * 1e-10)
+
+
+def draw_models(n: int, seed: int = BATCH_SEED, lmax_range=(1500, 5000), nk_range=(2000, 8000)):
+    """Per-model draws, in this order for each model: lmax, nk, tau*, width, ISW amp, n_s, ln(1e10 A_s)."""
+    rng = np.random.default_rng(seed)
+    out: List[ModelDraw] = []
+    for _ in range(n):
+        lmax = int(rng.integers(lmax_range[0], lmax_range[1] + 1))
+        nk = int(rng.integers(nk_range[0], nk_range[1] + 1))
+        out.append(ModelDraw(lmax=lmax, nk=nk, tau_star=float(rng.uniform(260.0, 300.0)),
+                             width=float(rng.uniform(15.0, 25.0)), a_isw=float(rng.uniform(0.0, 0.2)),
+                             n_s=float(rng.uniform(0.92, 1.0)),
+                             ln1e10As=float(rng.uniform(2.9, 3.2))))
+    return out
+
+
+def master_indices(nk_model: int, master_nk: int = MASTER_NK) -> np.ndarray:
+    """Model k-grid as a subset of the shared master grid: round(j (M-1)/(n-1))."""
+    j = np.arange(nk_model, dtype=np.float64)
+    return np.rint(j * (master_nk - 1) / (nk_model - 1)).astype(np.int64)
+
+
+def model_workload(d: ModelDraw, ntau: int = 3000, master_nk: int = MASTER_NK,
+                   master_kmax: float = MASTER_KMAX, kmin: float = 1e-4) -> Workload:
+    """One drawn model as a stand-alone workload on its own subset of the master k grid."""
+    kmaster = log_k_grid(master_nk, kmin, master_kmax)
+    idx = master_indices(d.nk, master_nk)
+    k = kmaster[idx]
+    tau = tau_grid(ntau)
+    return Workload(name="model", lmin=2, lmax=d.lmax, k=k, tau=tau, tau0=TAU0,
+                    w_tau=trapezoid_weights(tau), w_lnk=trapezoid_weights(np.log(k)),
+                    Pk=primordial(k, d.A_s, d.n_s),
+                    S=sources(k, tau, 3, tau_star=d.tau_star, width=d.width, a_isw=d.a_isw),
+                    pairs=PAIRS_4, pair_names=PAIR_NAMES_4,
+                    params=dict(A_s=d.A_s, n_s=d.n_s, tau_star=d.tau_star, width=d.width,
+                                a_isw=d.a_isw))
