@@ -1,0 +1,177 @@
+"""Benchmark: LOS projection + C_l on one MI355X (FP64 plain path).
+
+One step = los_project (Eq. 2-3) + cl_integrate (Eq. 1) for one model of the
+benchmark workload (default C2: T/E/lensing sources, l = 2..2500, 4000 log-k
+on [1e-4, 0.5], 3000 tau on [0, 14000]; outputs TT, EE, TE, phi-phi), with all
+inputs resident in HBM.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config C2] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "C_ℓ spectra/s and Δ_ℓ(k) GFMA/s vs FP64 plain path at ≤1e-4 rel err"
+PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_cl_oracle.txt")
+
+
+def tp_and_band_counts(wl):
+    """Per-launch work counts over all (k, tau) pairs (host-side counting only).
+    TP: l in [lmin, lmax] with x = k (tau0 - tau) >= l + 1/2 (the oscillatory, threshold-free set).
+    band: l up to the kernel's cut x + 14.2 x^(1/3) + 9.5."""
+    chi = wl.tau0 - wl.tau
+    tp = 0
+    band = 0
+    for i in range(0, wl.nk, 256):
+        x = wl.k[i:i + 256, None] * chi[None, :]
+        top = np.minimum(np.floor(x - 0.5), wl.lmax)
+        tp += int(np.sum(np.maximum(top - wl.lmin + 1, 0)))
+        cut = np.minimum(np.floor(x + 14.2 * np.cbrt(x) + 9.5), wl.lmax)
+        band += int(np.sum(np.maximum(cut - wl.lmin + 1, 0)))
+    return tp, band
+
+
+def cpu_baseline(wl, stride):
+    import oracle
+    rows = np.arange(0, wl.nk, stride)
+    S = np.ascontiguousarray(wl.S[:, rows, :])
+    t0 = time.perf_counter()
+    d = oracle.project(wl.lmin, wl.lmax, wl.k[rows], wl.tau, wl.tau0, wl.w_tau, S)
+    oracle.cl(d, wl.w_lnk[rows], wl.Pk[rows], wl.pairs)
+    dt = time.perf_counter() - t0
+    per_spectrum = dt * wl.nk / rows.size
+    return {"value": 1.0 / per_spectrum, "unit": "spectra/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d of %d k rows (every %dth), all l and tau, %.1f s; scaled by nk/rows"
+                      % (rows.size, wl.nk, stride, dt)}
+
+
+def golden_error(c, wl):
+    if wl.name != "C2" or not os.path.exists(GOLDEN):
+        return None
+    g = np.loadtxt(GOLDEN)
+    ls = g[:, 0].astype(int) - wl.lmin
+    worst = 0.0
+    for p, (a, b) in enumerate(wl.pairs):
+        ref = g[:, 1 + p]
+        if a == b:
+            rel = np.abs(c[p, ls] / ref - 1)
+        else:
+            rel = np.abs(c[p, ls] - ref) / np.sqrt(g[:, 1 + wl.pairs.index((a, a))] *
+                                                   g[:, 1 + wl.pairs.index((b, b))])
+        worst = max(worst, float(np.max(rel)))
+    return worst
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the projection shards over k; see "
+              "DESIGN.md); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    from paper_2509_25110_amd import inputs, los
+
+    torch.cuda.set_device(0)
+    wl = inputs.config(args.config)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    k, tau, w, S = dv(wl.k), dv(wl.tau), dv(wl.w_tau), dv(wl.S)
+    wk, Pk = dv(wl.w_lnk), dv(wl.Pk)
+    delta = torch.empty((wl.nk, wl.nl, wl.nsrc), dtype=torch.float64, device="cuda")
+    cl = torch.empty((len(wl.pairs), wl.nl), dtype=torch.float64, device="cuda")
+    ctx = los.Context()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, delta=delta)
+        ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(max(args.warmup - 1, 0)):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(stream)
+    for i in range(K):
+        ev[i][0].record(stream)
+        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, delta=delta)
+        ev[i][1].record(stream)
+        ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = start.elapsed_time(end)
+    proj_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms_per_step = total_ms / K
+
+    tp, band = tp_and_band_counts(wl)
+    flops = tp * (3.0 + 2.0 * wl.nsrc)  # recurrence FMA + coefficient add, nsrc FMAs, per TP entry
+    achieved = flops / (proj_ms * 1e-3) / 1e12
+    gfma = wl.nsrc * tp / (ms_per_step * 1e-3) / 1e9
+    err = golden_error(cl.cpu().numpy(), wl)
+
+    out = {
+        "metric": METRIC,
+        "value": K / (total_ms * 1e-3),
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s, FP64 plain path" % (wl.name, inputs.DESCRIPTIONS[wl.name]),
+                   "nk": wl.nk, "ntau": wl.ntau, "lmax": wl.lmax, "nsrc": wl.nsrc,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "project_fp64_kernel", "kernel_ms": proj_ms,
+                     "work": "%d TP (l,k,tau) entries x %d FP64 flops" % (tp, 3 + 2 * wl.nsrc)},
+        "gfma_per_s": gfma,
+        "tp_entries": tp,
+        "band_entries": band,
+        "first_call_ms": first_ms,
+        "cl_ms": ms_per_step - proj_ms,
+        "wall_s_timed": wall,
+        "max_rel_err_vs_oracle": err,
+    }
+    if not args.no_cpu_baseline and rank == 0:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_stride)
+    ctx.close()
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,140 @@
+/*
+ * los.h -- C ABI of liblos.so, an MI355X (gfx950) implementation of the
+ * line-of-sight (LOS) projection and angular power spectrum of a flat-space
+ * Einstein-Boltzmann solver.
+ *
+ * The operations are the ones the gCAMB paper states (Storchi et al., arXiv
+ * 2509.25110):
+ *   Sec. 2.1, Eq. 2-3: Delta^X_l(k) = int dtau S_X(k, tau) j_l(k (tau0 - tau)),
+ *                      discretised as sum_n w_n S_X(k, tau_n) j_l(k chi_n),
+ *                      chi_n = tau0 - tau_n, with spherical Bessel kernels j_l
+ *                      (flat space, text below Eq. 3);
+ *   Sec. 2.1, Eq. 1:   C^XY_l = 4 pi int dk/k P(k) Delta^X_l Delta^Y_l,
+ *                      discretised as 4 pi sum_i w_i P(k_i) Delta^X_l Delta^Y_l
+ *                      with w_i the caller's ln k quadrature weights;
+ *   Sec. 3.2 / Algorithm 1: the work is independent per k ("gang"), and per k
+ *                      over l and over tau ("vector").
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer (hipMalloc / torch CUDA tensor)
+ *     unless its comment says "host".  The caller owns all of them; the
+ *     library never frees or retains them after the call returns.
+ *   - Arrays are dense row-major; index formulas are given per argument.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on that stream and returns; results are ready when the
+ *     stream is synchronised.
+ *   - Return value: LOS_OK (0) or a los_status error code.  Argument errors
+ *     are detected before anything is launched (LOS_ERR_INVALID, nothing is
+ *     written).  los_last_error() returns a message for the calling thread's
+ *     most recent failure (valid until that thread's next call).
+ *   - A los_ctx owns the library's device workspace (grown on demand and
+ *     reused).  A context is not thread-safe: use one per host thread, and do
+ *     not run two calls of one context concurrently on different streams.
+ *   - Floating point: FP64 entry points compute in IEEE double; results agree
+ *     with a plain FP64 evaluation of the formulas above to about 1e-12
+ *     (normwise); entries smaller than ~1e-20 of the local peak of j_l are
+ *     treated as zero (band cut), see los_bessel_table.
+ */
+#ifndef LOS_H
+#define LOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LOS_OK = 0,
+    LOS_ERR_INVALID = 1,     /* bad argument; nothing launched               */
+    LOS_ERR_HIP = 2,         /* HIP runtime or launch failure                */
+    LOS_ERR_OOM = 3,         /* device workspace allocation failed           */
+    LOS_ERR_UNSUPPORTED = 4, /* valid request outside what is implemented    */
+    LOS_ERR_NUMERIC = 5      /* reserved: non-finite result detected         */
+} los_status;
+
+typedef enum {
+    LOS_FP64 = 0,   /* IEEE double throughout                                 */
+    LOS_FP32 = 1,   /* reserved: FP32 projection GEMM on MFMA, FP64 j_l       */
+    LOS_BF16X3 = 2  /* reserved: split-BF16x3 projection GEMM on MFMA         */
+} los_prec;
+
+typedef struct los_ctx los_ctx;
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *los_last_error(void);
+
+/* Library version string (host, static storage). */
+const char *los_version(void);
+
+/* Create a context bound to the current HIP device.  *ctx receives a handle
+ * owned by the caller and released with los_ctx_destroy.  Errors:
+ * LOS_ERR_INVALID (ctx == NULL), LOS_ERR_HIP (no device). */
+int los_ctx_create(los_ctx **ctx);
+
+/* Release a context and its device workspace.  Waits for nothing: the caller
+ * must make sure no work that uses the context is still queued.  NULL is a
+ * no-op. */
+void los_ctx_destroy(los_ctx *ctx);
+
+/*
+ * Spherical Bessel table (the radial kernel of Eq. 2-3, flat space).
+ *
+ *   out[(l - lmin) * nx + i] = j_l(x[i]),   l = lmin..lmax, i = 0..nx-1
+ *
+ * x: device, nx doubles, each finite and >= 0.  out: device, (lmax-lmin+1)*nx
+ * doubles.  0 <= lmin <= lmax <= 30000, nx >= 0 (nx == 0 is a no-op).
+ * Method: upward recurrence from j_0 = sin x / x (and j_{-1} = cos x / x) up to
+ * l = floor(x); above that, Miller's downward recurrence started above the
+ * turning point and matched to the upward value at l = floor(x).  Values with
+ * l above x + 14.2 x^(1/3) + 9.5 (where |j_l| < ~1e-21 of its peak) are
+ * returned as 0; for x < 1e-9 the first three power-series terms are used.
+ * Errors: LOS_ERR_INVALID for NULL pointers or bad ranges (values of x are
+ * not inspected on the host; a negative or non-finite x yields NaN there).
+ */
+int los_bessel_table(los_ctx *ctx, const double *x, int64_t nx, int32_t lmin, int32_t lmax,
+                     double *out, void *stream);
+
+/*
+ * LOS projection, Eq. 2-3 (Algorithm 1: one workgroup per k, lanes over tau,
+ * an l recurrence per lane).
+ *
+ *   delta[(i * nl + (l - lmin)) * nsrc + s]
+ *       = sum_n w_tau[n] * S[(s * nk + i) * ntau + n] * j_l(k[i] * (tau0 - tau[n]))
+ *
+ *   nl = lmax - lmin + 1, i = 0..nk-1, s = 0..nsrc-1.
+ *
+ * k: device, nk doubles (> 0).  tau, w_tau: device, ntau doubles, with
+ * tau[n] <= tau0.  S: device, nsrc*nk*ntau values.  delta: device,
+ * nk*nl*nsrc values.  For prec == LOS_FP64, S and delta are double.
+ * Limits: 2 <= lmin <= lmax <= 16000, 1 <= nsrc <= 4, 1 <= ntau <= 8192,
+ * nk >= 1.  Other precisions: LOS_ERR_UNSUPPORTED.
+ * The j_l are generated on the fly (never stored); the band where
+ * |j_l| < ~1e-21 of its peak is skipped.
+ */
+int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
+                const double *k, const double *tau, const double *w_tau, const void *S,
+                int32_t nsrc, int32_t prec, void *delta, void *stream);
+
+/*
+ * Angular power spectra, Eq. 1 with the ln k quadrature written out:
+ *
+ *   cl[p * nl + l'] = 4 pi sum_i w_lnk[i] * Pk[i]
+ *                          * delta[(i * nl + l') * nsrc + a_p] * delta[(i * nl + l') * nsrc + b_p]
+ *
+ * delta: device, nk*nl*nsrc values, double if delta_prec == LOS_FP64 and
+ * float if LOS_FP32.  w_lnk, Pk: device, nk doubles.  pairs: HOST, 2*npairs
+ * int32 source indices {a_0, b_0, a_1, b_1, ...}, each in [0, nsrc).
+ * cl: device, npairs*nl doubles.  Accumulation is FP64 in a fixed order (the
+ * result is bitwise reproducible for a given shape).  1 <= nsrc <= 4,
+ * 1 <= npairs <= 16, nl >= 1, nk >= 1.
+ */
+int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc, int32_t nl,
+                 int64_t nk, const double *w_lnk, const double *Pk, const int32_t *pairs,
+                 int32_t npairs, double *cl, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOS_H */

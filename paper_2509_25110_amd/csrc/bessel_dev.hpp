@@ -1,0 +1,37 @@
+// Device-side helpers for the spherical Bessel kernels j_l(x) of the
+// line-of-sight integrals (gCAMB paper, Sec. 2.1 Eq. 2-3: flat space, so the
+// radial kernel is j_l).
+//
+// Per argument x the library uses two recurrences:
+//   * upward   j_{l+1} = (2l+1)/x j_l - j_{l-1} from j_{-1} = cos x / x and
+//              j_0 = sin x / x, for l <= m = floor(x) (oscillatory side, where
+//              the upward direction is stable);
+//   * Miller   the same recurrence run downward from a start above the
+//              turning point, for m < l <= ltop(x); it is scaled so that it
+//              passes through the upward value at l = m.
+// Above ltop(x) the values are below ~1e-21 of their peak and are dropped.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace los {
+
+// Below this x the first power-series terms are exact in FP64; the
+// projection treats such nodes as contributing nothing for l >= 2
+// (|j_2(x)| < 7e-20 there).
+constexpr double kXTiny = 1e-9;
+
+// Last l kept for argument x.  x + 14.2 x^(1/3) + 10 lies above the root in
+// nu of the Debye exponent nu*acosh(nu/x) - sqrt(nu^2 - x^2) = 50 for every
+// x >= 1e-3 (margin 5 to 12 in nu), so |j_l(x)| < ~1e-21 of its peak for
+// l + 1/2 beyond it.
+__device__ inline int ltop_of(double x) {
+  return (int)floor(x + 14.2 * cbrt(x) + 9.5);
+}
+
+// One step of the three-term recurrence with coefficient t = (2l+1)/x:
+// returns t*c - p.
+__device__ inline double rec_step(double t, double c, double p) { return fma(t, c, -p); }
+
+}  // namespace los

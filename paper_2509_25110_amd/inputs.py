@@ -98,6 +98,8 @@ def lensing_kernel(tau: np.ndarray) -> np.ndarray:
 
 def sources(k: np.ndarray, tau: np.ndarray, nsrc: int, tau_star=280.0, width=20.0, a_isw=0.1):
     """Synthetic S[src, k, tau]: T, then E = 0.5 k^2 g(tau), then the lensing kernel."""
+    if not 1 <= nsrc <= 3:
+        raise ValueError("synthetic sources exist for nsrc = 1..3")
     g = gauss(tau, tau_star, width)[None, :]
     kk = k[:, None]
     S = np.empty((nsrc, k.size, tau.size), dtype=np.float64)
@@ -112,8 +114,9 @@ def sources(k: np.ndarray, tau: np.ndarray, nsrc: int, tau_star=280.0, width=20.
 def _make(name, lmax, nk, kmax, ntau, nsrc, kmin=1e-4, A_s=2.1e-9, n_s=0.965, **src_kw):
     k = log_k_grid(nk, kmin, kmax)
     tau = tau_grid(ntau)
-    pairs = PAIRS_TT if nsrc == 1 else PAIRS_4
-    names = ("TT",) if nsrc == 1 else PAIR_NAMES_4
+    keep = [i for i, (a, b) in enumerate(PAIRS_4) if a < nsrc and b < nsrc]
+    pairs = tuple(PAIRS_4[i] for i in keep)
+    names = tuple(PAIR_NAMES_4[i] for i in keep)
     return Workload(name=name, lmin=2, lmax=lmax, k=k, tau=tau, tau0=TAU0,
                     w_tau=trapezoid_weights(tau), w_lnk=trapezoid_weights(np.log(k)),
                     Pk=primordial(k, A_s, n_s), S=sources(k, tau, nsrc, **src_kw),

@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/los.h declares, and rejects bad arguments before touching HIP."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "los.h")
+LIB = os.path.join(ROOT, "paper_2509_25110_amd", "liblos.so")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2509_25110_amd import build
+        build.build(verbose=False)
+    from paper_2509_25110_amd import los
+    return los.load_library(LIB)
+
+
+def test_header_lists_expected_entry_points():
+    names = header_functions()
+    for n in ("los_bessel_table", "los_project", "cl_integrate", "los_ctx_create",
+              "los_ctx_destroy", "los_last_error", "los_version"):
+        assert n in names, names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), "liblos.so does not export %s" % name
+    from paper_2509_25110_amd import los
+    assert set(los.EXPORTS) == set(header_functions())
+
+
+def test_version_and_empty_error(lib):
+    assert b"gfx950" in lib.los_version()
+    assert isinstance(lib.los_last_error(), bytes)
+
+
+def _dummy_ctx():
+    # validation runs before the context is used, so any non-NULL handle works here
+    buf = ctypes.create_string_buffer(64)
+    return ctypes.cast(buf, ctypes.c_void_p), buf
+
+
+def test_null_context_rejected(lib):
+    rc = lib.los_project(None, 2, 10, 4, 8, 1.0, None, None, None, None, 1, 0, None, None)
+    assert rc == 1 and b"ctx" in lib.los_last_error()
+    rc = lib.los_bessel_table(None, None, 1, 0, 3, None, None)
+    assert rc == 1
+    rc = lib.los_ctx_create(None)
+    assert rc == 1
+
+
+def test_project_argument_validation(lib):
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation
+    cases = [
+        dict(lmin=1, lmax=10),          # lmin < 2
+        dict(lmin=10, lmax=9),          # lmax < lmin
+        dict(lmax=20000),               # lmax too large
+        dict(nk=0),
+        dict(ntau=0),
+        dict(ntau=9000),                # beyond the supported tau grid
+        dict(nsrc=0),
+        dict(nsrc=5),
+        dict(prec=7),                   # unknown precision
+    ]
+    for c in cases:
+        a = dict(lmin=2, lmax=10, nk=4, ntau=8, nsrc=1, prec=0)
+        a.update(c)
+        rc = lib.los_project(ctx, a["lmin"], a["lmax"], a["nk"], a["ntau"], 1.0, p, p, p, p,
+                             a["nsrc"], a["prec"], p, None)
+        assert rc == 1, (c, rc, lib.los_last_error())
+    rc = lib.los_project(ctx, 2, 10, 4, 8, 1.0, p, None, p, p, 1, 0, p, None)
+    assert rc == 1 and b"NULL" in lib.los_last_error()
+
+
+def test_unsupported_precision_reported(lib):
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("uses a dummy context and pointers; only run where nothing can launch")
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)
+    rc = lib.los_project(ctx, 2, 10, 4, 8, 1.0, p, p, p, p, 1, 2, p, None)
+    assert rc == 4 and b"not implemented" in lib.los_last_error()
+
+
+def test_cl_and_table_validation(lib):
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)
+    pairs = (ctypes.c_int32 * 2)(0, 3)
+    assert lib.cl_integrate(ctx, p, 0, 2, 10, 4, p, p, pairs, 1, p, None) == 1  # index 3 >= nsrc
+    pairs = (ctypes.c_int32 * 2)(0, 0)
+    assert lib.cl_integrate(ctx, p, 0, 0, 10, 4, p, p, pairs, 1, p, None) == 1  # nsrc = 0
+    assert lib.cl_integrate(ctx, p, 0, 1, 10, 4, p, p, pairs, 17, p, None) == 1  # npairs > 16
+    assert lib.cl_integrate(ctx, p, 9, 1, 10, 4, p, p, pairs, 1, p, None) == 1  # bad delta prec
+    assert lib.los_bessel_table(ctx, p, 5, 4, 3, p, None) == 1                   # lmax < lmin
+    assert lib.los_bessel_table(ctx, p, -1, 0, 3, p, None) == 1                  # nx < 0
+    assert lib.los_bessel_table(ctx, None, 0, 0, 3, None, None) == 0             # nx == 0: no-op

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (FP64 path, derived in the design doc): C_l elementwise 1e-10 relative
+(TE relative to sqrt(TT EE)); Delta normwise 1e-10 per (l, source), i.e.
+max_k |Delta - Delta_ref| <= 1e-10 max_k A with A = sum_n |w_n S j_l| (the
+oracle's absolute sum), which also covers entries the band cut drops.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_25110_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_cl_oracle.txt")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_2509_25110_amd import los
+    c = los.Context()
+    yield c
+    c.close()
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def run_gpu(torch, ctx, wl, S=None):
+    S = wl.S if S is None else S
+    d = ctx.los_project(wl.lmin, wl.lmax, dev(torch, wl.k), dev(torch, wl.tau), wl.tau0,
+                        dev(torch, wl.w_tau), dev(torch, S))
+    c = ctx.cl_integrate(d, dev(torch, wl.w_lnk), dev(torch, wl.Pk), wl.pairs)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), c.cpu().numpy()
+
+
+def assert_delta_normwise(d, ref, A, tol=1e-10):
+    scale = np.max(A, axis=0, keepdims=True)
+    err = np.abs(d - ref) / np.maximum(scale, 1e-300)
+    worst = np.unravel_index(np.argmax(err), err.shape)
+    assert np.max(err) <= tol, ("delta normwise", float(np.max(err)), worst)
+
+
+def assert_cl(c, cref, pairs, tol=1e-10):
+    for p, (a, b) in enumerate(pairs):
+        if a == b:
+            rel = np.abs(c[p] / cref[p] - 1)
+        else:
+            ia = pairs.index((a, a))
+            ib = pairs.index((b, b))
+            rel = np.abs(c[p] - cref[p]) / np.sqrt(cref[ia] * cref[ib])
+        assert np.max(rel) <= tol, ("C_l", p, float(np.max(rel)), int(np.argmax(rel)))
+
+
+def check_workload(torch, ctx, wl, tol=1e-10):
+    d, c = run_gpu(torch, ctx, wl)
+    ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S, with_abs=True)
+    assert np.all(np.isfinite(d))
+    assert_delta_normwise(d, ref, A, tol)
+    if len(wl.pairs) == 1 or all((a, a) in wl.pairs for p in wl.pairs for a in p):
+        assert_cl(c, oracle.cl(ref, wl.w_lnk, wl.Pk, wl.pairs), list(wl.pairs), tol)
+    return d, c
+
+
+# ---------------------------------------------------------------- Bessel table
+
+@pytest.mark.parametrize("lmin,lmax", [(0, 3000), (2, 700), (37, 41)])
+def test_bessel_table_vs_oracle(torch_dev, ctx, lmin, lmax):
+    torch = torch_dev
+    x = np.array([0.0, 1e-12, 5e-10, 2e-9, 1e-5, 0.3, 1.0, 2.5, 17.0, 123.4, 699.5, 700.5, 999.9,
+                  2499.3, 2500.7, 2999.99, 3000.01, 4321.0, 7000.0, 13999.9])
+    got = ctx.los_bessel_table(dev(torch, x), lmin, lmax).cpu().numpy()
+    ref = oracle.bessel_table(x, lmin, lmax)
+    full = oracle.bessel_table(x, 0, lmax)
+    for i in range(x.size):
+        env = max(np.max(np.abs(full[:, i])), 1e-300)
+        err = np.max(np.abs(got[:, i] - ref[:, i])) / env
+        assert err <= 1e-12, (x[i], err)
+
+
+def test_bessel_table_empty_and_tiny(torch_dev, ctx):
+    torch = torch_dev
+    out = ctx.los_bessel_table(dev(torch, np.zeros(0)), 0, 5)
+    assert out.numel() == 0
+    got = ctx.los_bessel_table(dev(torch, np.array([0.0, 1e-10])), 0, 4).cpu().numpy()
+    assert got[0, 0] == 1.0 and np.all(got[1:, 0] == 0.0)
+    assert abs(got[1, 1] - 1e-10 / 3) < 1e-25
+
+
+# ---------------------------------------------------------------- projection + C_l
+
+SMALL = [
+    dict(lmax=61, nk=12, kmax=0.02, ntau=300, nsrc=3),             # ragged l blocks
+    dict(lmax=130, nk=10, kmax=0.03, ntau=700, nsrc=1),            # two waves, ragged tau
+    dict(lmax=200, nk=9, kmax=0.05, ntau=1000, nsrc=2),
+    dict(lmax=90, nk=7, kmax=0.2, ntau=190, nsrc=4, kmin=0.01),    # x >> lmax for most nodes
+    dict(lmax=333, nk=16, kmax=0.1, ntau=2500, nsrc=3),            # four waves
+    dict(lmax=50, nk=5, kmax=1e-3, ntau=64, nsrc=3),               # small x everywhere
+]
+
+
+@pytest.mark.parametrize("cfg", SMALL, ids=[str(i) for i in range(len(SMALL))])
+def test_project_small_vs_oracle(torch_dev, ctx, cfg):
+    cfg = dict(cfg)
+    nsrc = cfg.pop("nsrc")
+    wl = inputs.small(nsrc=min(nsrc, 3), **cfg)
+    if nsrc == 4:  # a fourth, non-separable source
+        rng = np.random.default_rng(11)
+        S = np.concatenate([wl.S, rng.normal(size=(1, wl.nk, wl.ntau)) * wl.S[:1]], axis=0)
+        wl.S = S
+        wl.pairs = inputs.PAIRS_4 + ((3, 3), (0, 3))
+    check_workload(torch_dev, ctx, wl)
+
+
+def test_project_c1_full(torch_dev, ctx):
+    """Config C1 at full size (TT, l = 2..300, 400 k, 600 tau)."""
+    check_workload(torch_dev, ctx, inputs.config("C1"))
+
+
+@pytest.mark.parametrize("waves,slots", [(1, 12), (2, 8), (4, 4), (3, 12), (5, 4)])
+def test_project_launch_shapes_agree(torch_dev, ctx, waves, slots, monkeypatch):
+    torch = torch_dev
+    wl = inputs.small(lmax=140, nk=6, kmax=0.05, ntau=700, nsrc=3)
+    monkeypatch.setenv("LOS_PROJ_WAVES", str(waves))
+    monkeypatch.setenv("LOS_PROJ_SLOTS", str(slots))
+    d, _ = run_gpu(torch, ctx, wl)
+    monkeypatch.delenv("LOS_PROJ_WAVES")
+    monkeypatch.delenv("LOS_PROJ_SLOTS")
+    ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S, with_abs=True)
+    assert_delta_normwise(d, ref, A)
+
+
+def test_project_deterministic(torch_dev, ctx):
+    torch = torch_dev
+    wl = inputs.small(lmax=400, nk=20, kmax=0.08, ntau=1500, nsrc=3)
+    d1, c1 = run_gpu(torch, ctx, wl)
+    d2, c2 = run_gpu(torch, ctx, wl)
+    np.testing.assert_array_equal(d1, d2)
+    np.testing.assert_array_equal(c1, c2)
+
+
+def test_project_edge_cases(torch_dev, ctx):
+    torch = torch_dev
+    # one k, one l, lmin > 2, a tau grid with x = 0 at the last node and one tau node
+    for lmin, lmax, nk, ntau in [(2, 2, 1, 5), (37, 37, 3, 129), (5, 70, 2, 1), (2, 9, 4, 64),
+                                 (150, 160, 3, 200)]:
+        wl = inputs.small(lmax=lmax, nk=nk, kmax=0.05, ntau=max(ntau, 2), nsrc=3)
+        wl.lmin = lmin
+        if ntau == 1:
+            wl.tau = wl.tau[:1]
+            wl.w_tau = np.array([7.0])
+            wl.S = wl.S[:, :, :1].copy()
+        d, _ = run_gpu(torch, ctx, wl)
+        ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S,
+                                with_abs=True)
+        assert_delta_normwise(d, ref, A)
+
+
+def test_invalid_arguments_raise(torch_dev, ctx):
+    torch = torch_dev
+    from paper_2509_25110_amd import los
+    wl = inputs.small(lmax=20, nk=3, ntau=64, nsrc=1)
+    with pytest.raises(los.LosError) as e:
+        ctx.los_project(1, 20, dev(torch, wl.k), dev(torch, wl.tau), wl.tau0, dev(torch, wl.w_tau),
+                        dev(torch, wl.S))
+    assert e.value.code == los.LOS_ERR_INVALID
+
+
+def test_cl_integrate_vs_oracle(torch_dev, ctx):
+    torch = torch_dev
+    wl = inputs.small(lmax=300, nk=500, kmax=0.1, ntau=400, nsrc=3)
+    ref = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S)
+    pairs = list(wl.pairs) + [(1, 0), (2, 0)]
+    cref = oracle.cl(ref, wl.w_lnk, wl.Pk, pairs)
+    c = ctx.cl_integrate(dev(torch, ref), dev(torch, wl.w_lnk), dev(torch, wl.Pk), pairs).cpu().numpy()
+    scale = np.sqrt(np.abs(oracle.cl(ref, wl.w_lnk, wl.Pk, [(a, a) for a, _ in pairs]) *
+                           oracle.cl(ref, wl.w_lnk, wl.Pk, [(b, b) for _, b in pairs])))
+    assert np.max(np.abs(c - cref) / scale) <= 1e-13
+    # FP32 transfer functions: same sums over the float32-rounded values
+    ref32 = ref.astype(np.float32)
+    cref32 = oracle.cl(ref32.astype(np.float64), wl.w_lnk, wl.Pk, pairs)
+    c32 = ctx.cl_integrate(dev(torch, ref32), dev(torch, wl.w_lnk), dev(torch, wl.Pk),
+                           pairs).cpu().numpy()
+    assert np.max(np.abs(c32 - cref32) / scale) <= 1e-13
+
+
+# ---------------------------------------------------------------- full benchmark size
+
+def test_c2_full_size_sampled(torch_dev, ctx):
+    """The benchmark workload (C2: l = 2..2500, 4000 k, 3000 tau, T/E/lensing) in the launch
+    configuration bench.py times: C_l at the golden multipoles, Delta at sampled k rows."""
+    torch = torch_dev
+    wl = inputs.config("C2")
+    d, c = run_gpu(torch, ctx, wl)
+    assert np.all(np.isfinite(d)) and np.all(np.isfinite(c))
+    gold = np.loadtxt(GOLDEN)
+    ls = gold[:, 0].astype(int)
+    cref = np.zeros((4, wl.nl))
+    cref[:, ls - wl.lmin] = gold[:, 1:].T
+    cs = c[:, ls - wl.lmin]
+    cg = cref[:, ls - wl.lmin]
+    for p, (a, b) in enumerate(wl.pairs):
+        if a == b:
+            rel = np.abs(cs[p] / cg[p] - 1)
+        else:
+            rel = np.abs(cs[p] - cg[p]) / np.sqrt(cg[a] * cg[b])
+        assert np.max(rel) <= 1e-10, (wl.pair_names[p], float(np.max(rel)), ls[np.argmax(rel)])
+    rows = [0, 1, 700, 1999, 2600, 3100, 3500, 3800, 3998, 3999]
+    refs, As = [], []
+    for r in rows:
+        ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S,
+                                with_abs=True, k_range=(r, r + 1))
+        refs.append(ref[0])
+        As.append(A[0])
+    # per (l, source) scale over the sampled rows: a lower bound of the max over all k
+    scale = np.maximum(np.max(np.stack(As), axis=0), 1e-300)
+    for r, ref in zip(rows, refs):
+        err = np.max(np.abs(d[r] - ref) / scale)
+        assert err <= 1e-10, (r, err)
