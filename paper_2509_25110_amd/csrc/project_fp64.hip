@@ -24,6 +24,10 @@
 
 #include <climits>
 
+#ifndef LOS_IX_REG
+#define LOS_IX_REG 0
+#endif
+
 namespace los {
 namespace {
 
@@ -61,8 +65,17 @@ __device__ inline double swap_add16(double a, double b) {
 // wave's [NV][16] LDS area, `cross` the [W][NV] area of the current parity.
 template <int NV>
 __device__ inline double wg_reduce(double (&v)[NV], double *stage, double *cross, int W, int w,
-                                   int lane) {
+                                   int lane, bool wave_active = true) {
   static_assert(NV % 4 == 0, "NV must be a multiple of 4");
+  if (!wave_active) {  // uniform: this wave contributed nothing to the block
+    if (lane < NV) cross[w * NV + lane] = 0.0;
+    __syncthreads();
+    double all = 0.0;
+    if (w == 0 && lane < NV) {
+      for (int ww = 0; ww < W; ++ww) all += cross[ww * NV + lane];
+    }
+    return all;
+  }
   double u[NV / 2];
 #pragma unroll
   for (int p = 0; p < NV / 2; ++p) u[p] = swap_add32(v[p], v[p + NV / 2]);
@@ -88,18 +101,89 @@ __device__ inline double wg_reduce(double (&v)[NV], double *stage, double *cross
   return all;
 }
 
-// Load w_n * S[s][k][n] for this lane's node n.  The byte offset is passed
-// through an empty asm so the compiler recomputes SGPR-base + 32-bit offset
-// addressing in the loop instead of keeping one 64-bit address per slot and
-// source live across it.
+// Load S[s][k][n] for this lane's node n (zeros for padding lanes).  The byte
+// offset goes through an empty asm so the compiler recomputes SGPR-base +
+// 32-bit offset addressing in the loop instead of keeping one 64-bit address
+// per slot and source live across it.
 template <int NSRC>
-__device__ inline void load_ws(double (&sv)[NSRC], const double *const (&srow)[NSRC],
-                               const double *wv, int n) {
+__device__ inline void load_s(double (&sv)[NSRC], const double *const (&srow)[NSRC], int n,
+                              int ntau) {
   unsigned off = (unsigned)n * 8u;
   asm volatile("" : "+v"(off));
-  const double wn = *(const double *)((const char *)wv + off);
+  if (n < ntau) {
 #pragma unroll
-  for (int s = 0; s < NSRC; ++s) sv[s] = wn * *(const double *)((const char *)srow[s] + off);
+    for (int s = 0; s < NSRC; ++s) sv[s] = *(const double *)((const char *)srow[s] + off);
+  } else {
+#pragma unroll
+    for (int s = 0; s < NSRC; ++s) sv[s] = 0.0;
+  }
+}
+
+// Wave-uniform max / min of an int (result in a scalar register).
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Slot j's block thresholds live in lane j of a VGPR, so the set of slots to
+// run in a block is one compare + ballot, and each slot test is a scalar bit test.
+__device__ inline uint64_t slot_mask(bool pred) { return __ballot(pred); }
+__device__ inline bool has(uint64_t mask, int j) { return (mask >> j) & 1u; }
+
+// One slot of pass 1 over a block of B multipoles: outputs pc (= w j_l) for
+// l = b..b+B-1 into acc and advances (pa, pc) = (w j_{l-1}, w j_l).  With MASK,
+// only l <= m contributes (rel = m - b) and w j_m, the value the lane's Miller
+// part is matched to (j_m is near its last maximum in l, never near a zero),
+// is stored into *jm_out.
+template <int NSRC, int B, bool MASK>
+__device__ __forceinline__ void asc_slot(double (&acc)[B * NSRC], double &pa, double &pc,
+                                         double ix, const double (&sv)[NSRC], int b, int rel,
+                                         double *jm_out) {
+  double t = (double)(2 * b + 1) * ix;
+  const double d2 = ix + ix;
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    double o = pc;
+    if (MASK) {
+      o = i <= rel ? pc : 0.0;
+      if (i == rel) *jm_out = pc;
+    }
+#pragma unroll
+    for (int s = 0; s < NSRC; ++s) acc[i * NSRC + s] = fma(o, sv[s], acc[i * NSRC + s]);
+    const double nx = rec_step(t, pc, pa);
+    t += d2;
+    pa = pc;
+    pc = nx;
+  }
+}
+
+// One slot of pass 2 over the block [top-B+1, top], descending: outputs p0
+// (= j_l) and advances (p1, p0) = (j_{l+1}, j_l).  With MASK only l > m
+// contributes (rel = top - m); with ACC false the block is only advanced.
+template <int NSRC, int B, bool ACC, bool MASK>
+__device__ __forceinline__ void desc_slot(double (&acc)[B * NSRC], double &p1, double &p0,
+                                          double ix, const double (&sv)[NSRC], int top, int rel) {
+  double t = (double)(2 * top + 1) * ix;
+  const double d2 = ix + ix;
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    if (ACC) {
+      const int q = (B - 1 - i) * NSRC;
+      const double o = MASK ? (i < rel ? p0 : 0.0) : p0;
+#pragma unroll
+      for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(o, sv[s], acc[q + s]);
+    }
+    const double nx = rec_step(t, p0, p1);
+    t -= d2;
+    p1 = p0;
+    p0 = nx;
+  }
 }
 
 template <int NSRC, int T>
@@ -116,20 +200,31 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
   const int npad = W * 64 * T;
 
   double *ixs = lds;                       // [npad]  1/x per node
-  double *jms = lds + npad;                // [npad]  j_m, later the Miller seed
-  double *stage = lds + 2 * npad + w * NV * 16;  // per wave [NV][16]
-  double *cross0 = lds + 2 * npad + W * NV * 16; // [2][W][NV]
+  double *jms = lds + npad;                // [npad]  w j_m, later the Miller seed
+  uint32_t *mps = (uint32_t *)(lds + 2 * npad);  // [npad]  (m + 1) | (sblk + 1) << 16
+  double *const lds2 = lds + 2 * npad + (npad + 1) / 2;
+  double *stage = lds2 + w * NV * 16;      // per wave [NV][16]
+  double *cross0 = lds2 + W * NV * 16;     // [2][W][NV]
   int *bnd = (int *)(cross0 + 2 * W * NV);       // [3]
 
   const double kk = a.k[ki];
   const double *srow[NSRC];  // uniform row pointers of this k
 #pragma unroll
   for (int s = 0; s < NSRC; ++s) srow[s] = a.S + ((int64_t)s * a.nk + ki) * a.ntau;
-  const double *__restrict__ wv = a.w;
 
   // ---------------- per-node setup ----------------
-  uint32_t mp[T];  // (m + 1) | (sblk + 1) << 16 ; m = last upward l, sblk = Miller start block
+  // m = last row of the upward part, sblk = block of the Miller start, per node in mps
   double Ja[T], Jb[T];
+#if LOS_IX_REG
+  double Ix[T];  // 1/x per slot, kept in registers (read in every block)
+#define IXV(j, n) Ix[j]
+#else
+#define IXV(j, n) ixs[n]
+#endif
+  // Per-slot block thresholds (wave-uniform), held by lane j for slot j:
+  //   pass 1: slot runs unmasked in blocks bi <= thF, at all in blocks bi <= thA;
+  //   pass 2: slot is live in blocks thL <= bi <= thU, unmasked for bi >= thG.
+  int thF = -1, thA = -1, thL = INT_MAX, thU = -1, thG = INT_MAX;
   int my_mmax = -1, my_smax = -1, my_dlo = INT_MAX;
 #pragma unroll
   for (int j = 0; j < T; ++j) {
@@ -142,8 +237,11 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
         ix = 1.0 / x;
         double sn, cs;
         sincos(x, &sn, &cs);
-        pa = cs * ix;  // j_{-1}
-        pc = sn * ix;  // j_0
+        // The recurrence is linear, so the state carries w_n j_l: the weight
+        // of the tau quadrature is applied once here instead of per block.
+        const double wn = a.w[n];
+        pa = wn * (cs * ix);  // w j_{-1}
+        pc = wn * (sn * ix);  // w j_0
         const double fx = floor(x);
         m = fx >= (double)lmax ? lmax : (int)fx;
         jm = pc;
@@ -161,10 +259,34 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
       }
     }
     ixs[(w + W * j) * 64 + lane] = ix;
+#if LOS_IX_REG
+    Ix[j] = ix;
+#endif
     jms[(w + W * j) * 64 + lane] = jm;
-    mp[j] = (uint32_t)(m + 1) | ((uint32_t)(sblk + 1) << 16);
+    mps[(w + W * j) * 64 + lane] = (uint32_t)(m + 1) | ((uint32_t)(sblk + 1) << 16);
     Ja[j] = pa;
     Jb[j] = pc;
+    // wave-uniform bounds of this slot, so that per-block slot tests are scalar
+    {
+      const bool dsc = sblk >= 0;
+      const int mmax = wave_max(m), mmin = wave_min(m);
+      const int smax = wave_max(sblk);
+      const int dmin = wave_min(dsc ? m : INT_MAX), dmax = wave_max(dsc ? m : -1);
+      // unmasked in pass 1 while every lane has m >= b + B
+      const int f = mmin - lmin - B >= 0 ? (mmin - lmin - B) / B : -1;
+      const int ab = mmax >= lmin ? (mmax - lmin) / B : -1;
+      // live in pass 2 from the block holding row dmin + 1 up to the highest start block
+      const int lo = smax < 0 ? INT_MAX : (dmin + 1 <= lmin ? 0 : (dmin + 1 - lmin) / B);
+      // unmasked in pass 2 once b > dmax
+      const int g = smax < 0 ? INT_MAX : (dmax + 1 <= lmin ? 0 : (dmax + 1 - lmin + B - 1) / B);
+      if (lane == j) {
+        thF = f;
+        thA = ab;
+        thL = lo;
+        thU = smax;
+        thG = g;
+      }
+    }
     my_mmax = m > my_mmax ? m : my_mmax;
     if (sblk >= 0) {
       my_smax = sblk > my_smax ? sblk : my_smax;
@@ -191,58 +313,46 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
   const int asc_last = mmax_wg >= lmin ? (mmax_wg - lmin) / B : -1;
   for (int bi = 0; bi <= asc_last; ++bi) {
     const int b = lmin + bi * B;
+    const uint64_t fm = slot_mask(thF >= bi);               // unmasked slots
+    const uint64_t pm = slot_mask(thA >= bi) & ~fm;         // partially active slots
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    // Slots whose lanes all run through the whole block, then the partial ones:
+    // two single-sided branches keep acc in place (an if/else per slot makes the
+    // register allocator copy acc around every slot).
+    {
+      // sources of slot j+1 are loaded while slot j computes (L2 latency)
+      double sv[NSRC], svn[NSRC];
+      load_s<NSRC>(sv, srow, w * 64 + lane, ntau);
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        const int nb = (w + W * j) * 64;
+        if (nb >= ntau) break;
+        int n = nb + lane;
+        asm volatile("" : "+v"(n));
+        if (j + 1 < T) load_s<NSRC>(svn, srow, n + W * 64, ntau);
+        // fully upward through the block, and j_m (if needed) lies beyond it
+        if (has(fm, j)) asc_slot<NSRC, B, false>(acc, Ja[j], Jb[j], IXV(j, n), sv, b, 0, nullptr);
+#pragma unroll
+        for (int s = 0; s < NSRC; ++s) sv[s] = svn[s];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < T; ++j) {
       const int nb = (w + W * j) * 64;
       if (nb >= ntau) break;
       int n = nb + lane;
-      uint32_t mpj = mp[j];
-      asm volatile("" : "+v"(n), "+v"(mpj));  // keep only mp[j] live across blocks
-      const int m = (int)(mpj & 0xFFFFu) - 1;
-      if (!__any(m >= b)) continue;
-      // fully upward through the block, and j_m (if needed) lies beyond it
-      const bool full = __all(m >= b + B);
-      const double ix = ixs[n];
-      double sv[NSRC];
-      if (n < ntau) {
-        load_ws<NSRC>(sv, srow, wv, n);
-      } else {
-#pragma unroll
-        for (int s = 0; s < NSRC; ++s) sv[s] = 0.0;
-      }
-      double pa = Ja[j], pc = Jb[j];
-      double t = (double)(2 * b + 1) * ix;
-      const double d2 = ix + ix;
-      if (full) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-#pragma unroll
-          for (int s = 0; s < NSRC; ++s) acc[i * NSRC + s] = fma(pc, sv[s], acc[i * NSRC + s]);
-          const double nx = rec_step(t, pc, pa);
-          t += d2;
-          pa = pc;
-          pc = nx;
-        }
-      } else {
+      asm volatile("" : "+v"(n));
+      const uint32_t mpj = mps[n];
+      if (has(pm, j)) {
+        const int m = (int)(mpj & 0xFFFFu) - 1;
+        double sv[NSRC];
+        load_s<NSRC>(sv, srow, n, ntau);
         int rel = m - b;  // opaque, so the compiler does not precompute m - i per slot
         asm volatile("" : "+v"(rel));
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-          const double o = i <= rel ? pc : 0.0;
-          if (i == rel) jms[n] = pc;
-#pragma unroll
-          for (int s = 0; s < NSRC; ++s) acc[i * NSRC + s] = fma(o, sv[s], acc[i * NSRC + s]);
-          const double nx = rec_step(t, pc, pa);
-          t += d2;
-          pa = pc;
-          pc = nx;
-        }
+        asc_slot<NSRC, B, true>(acc, Ja[j], Jb[j], IXV(j, n), sv, b, rel, &jms[n]);
       }
-      Ja[j] = pa;
-      Jb[j] = pc;
     }
     const double tot = wg_reduce<NV>(acc, stage, cross0 + parity * W * NV, W, w, lane);
     parity ^= 1;
@@ -261,7 +371,9 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
 
   // ---------------- pass 2: Miller recurrence, descending blocks ----------------
   if (smax_wg < 0) return;  // uniform
-  // seed = j_m / (value reached at l = m by the recurrence started with (0, 1))
+  // Miller seed: the recurrence started from (0, 1) at the top of block sblk is
+  // run down to l = m (whole blocks, then single steps) and scaled to meet the
+  // upward value stored there.
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     Ja[j] = 0.0;
@@ -269,16 +381,31 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
     const int nb = (w + W * j) * 64;
     if (nb >= ntau) break;
     const int n = nb + lane;
-    const int m = (int)(mp[j] & 0xFFFFu) - 1;
-    const int sb = (int)(mp[j] >> 16) - 1;
+    const uint32_t mpj = mps[n];
+    const int m = (int)(mpj & 0xFFFFu) - 1;
+    const int sb = (int)(mpj >> 16) - 1;
     if (sb >= 0) {
-      const double ix = ixs[n];
-      const int ls = lmin + sb * B + B - 1;
+      const double ix = IXV(j, n);
+      const double d2 = ix + ix;
+      const int mt = m;
+      int l = lmin + sb * B + B - 1;
       double jp = 0.0, jc = 1.0;
-      for (int l = ls; l > m; --l) {
+      while (l - B >= mt) {  // whole blocks
+        double t = (double)(2 * l + 1) * ix;
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          const double nx = rec_step(t, jc, jp);
+          t -= d2;
+          jp = jc;
+          jc = nx;
+        }
+        l -= B;
+      }
+      while (l > mt) {
         const double nx = rec_step((double)(2 * l + 1) * ix, jc, jp);
         jp = jc;
         jc = nx;
+        --l;
       }
       jms[n] = jms[n] / jc;
     }
@@ -291,80 +418,66 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    // the stored pass-1 sum of this block is read now and added after the reduction
+    const bool mine = store && w == 0 && lane < NV && b + lane / NSRC <= lmax;
+    double old = 0.0;
+    if (mine) old = drow[(int64_t)(b - lmin) * NSRC + lane];
+    const uint64_t live = slot_mask(thL <= bi && bi <= thU);
+    const uint64_t gm0 = live & slot_mask(thG <= bi), gm1 = live & ~gm0;
+    const bool act = live != 0;  // wave-uniform: this wave has a live slot in the block
+    if (store) {
+      // pass over slots in two single-sided groups (see pass 1)
 #pragma unroll
-    for (int j = 0; j < T; ++j) {
-      const int nb = (w + W * j) * 64;
-      if (nb >= ntau) break;
-      int n = nb + lane;
-      uint32_t mpj = mp[j];
-      asm volatile("" : "+v"(n), "+v"(mpj));
-      const int m = (int)(mpj & 0xFFFFu) - 1;
-      const int sb = (int)(mpj >> 16) - 1;
-      if (!__any(sb >= bi && top > m)) continue;
-      const double ix = ixs[n];
-      double p1 = Ja[j], p0 = Jb[j];  // j_{top+1}, j_top
-      if (__any(sb == bi)) {
-        const double sd = jms[n];
+      for (int g = 0; g < 2; ++g) {
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const int nb = (w + W * j) * 64;
+          if (nb >= ntau) break;
+          int n = nb + lane;
+          asm volatile("" : "+v"(n));
+          const uint32_t mpj = mps[n];
+          // live: some lane has started its Miller part and reaches above its m;
+          // group 0: every Miller lane's upward range ends below the block
+          if (!has(g == 0 ? gm0 : gm1, j)) continue;
+          const int m = (int)(mpj & 0xFFFFu) - 1;
+          const int sb = (int)(mpj >> 16) - 1;
+          if (sb == bi) {  // Miller start of this lane
+            Ja[j] = 0.0;
+            Jb[j] = jms[n];
+          }
+          double sv[NSRC];
+          load_s<NSRC>(sv, srow, n, ntau);
+          if (g == 0) {
+            desc_slot<NSRC, B, true, false>(acc, Ja[j], Jb[j], IXV(j, n), sv, top, 0);
+          } else {
+            int rel = top - m;  // opaque, see pass 1
+            asm volatile("" : "+v"(rel));
+            desc_slot<NSRC, B, true, true>(acc, Ja[j], Jb[j], IXV(j, n), sv, top, rel);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        const int nb = (w + W * j) * 64;
+        if (nb >= ntau) break;
+        int n = nb + lane;
+        asm volatile("" : "+v"(n));
+        const uint32_t mpj = mps[n];
+        if (!has(live, j)) continue;
+        const int sb = (int)(mpj >> 16) - 1;
         if (sb == bi) {
-          p1 = 0.0;
-          p0 = sd;
+          Ja[j] = 0.0;
+          Jb[j] = jms[n];
         }
-      }
-      double t = (double)(2 * top + 1) * ix;
-      const double d2 = ix + ix;
-      if (!store) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-          const double nx = rec_step(t, p0, p1);
-          t -= d2;
-          p1 = p0;
-          p0 = nx;
-        }
-      } else {
         double sv[NSRC];
-        if (n < ntau) {
-          load_ws<NSRC>(sv, srow, wv, n);
-        } else {
-#pragma unroll
-          for (int s = 0; s < NSRC; ++s) sv[s] = 0.0;
-        }
-        if (__all(b > m)) {
-#pragma unroll
-          for (int i = 0; i < B; ++i) {
-            const int q = (B - 1 - i) * NSRC;
-#pragma unroll
-            for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
-            const double nx = rec_step(t, p0, p1);
-          t -= d2;
-            p1 = p0;
-            p0 = nx;
-          }
-        } else {
-          int rel = top - m;  // opaque, see pass 1
-          asm volatile("" : "+v"(rel));
-#pragma unroll
-          for (int i = 0; i < B; ++i) {
-            const int q = (B - 1 - i) * NSRC;
-            const double o = i < rel ? p0 : 0.0;
-#pragma unroll
-            for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(o, sv[s], acc[q + s]);
-            const double nx = rec_step(t, p0, p1);
-          t -= d2;
-            p1 = p0;
-            p0 = nx;
-          }
-        }
+        desc_slot<NSRC, B, false, false>(acc, Ja[j], Jb[j], IXV(j, n), sv, top, 0);
       }
-      Ja[j] = p1;
-      Jb[j] = p0;
     }
     if (store) {
-      const double tot = wg_reduce<NV>(acc, stage, cross0 + parity * W * NV, W, w, lane);
+      const double tot = wg_reduce<NV>(acc, stage, cross0 + parity * W * NV, W, w, lane, act);
       parity ^= 1;
-      if (w == 0 && lane < NV) {
-        const int l = b + lane / NSRC;
-        if (l <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] += tot;
-      }
+      if (mine) drow[(int64_t)(b - lmin) * NSRC + lane] = old + tot;
     }
   }
 }
@@ -388,6 +501,8 @@ hipError_t launch_n(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s)
     case 8: return launch_t<NSRC, 8>(a, sh, s);
     case 12: return launch_t<NSRC, 12>(a, sh, s);
     case 16: return launch_t<NSRC, 16>(a, sh, s);
+    case 24: return launch_t<NSRC, 24>(a, sh, s);
+    case 32: return launch_t<NSRC, 32>(a, sh, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -404,12 +519,14 @@ ProjectShape project_fp64_shape(int nsrc, int64_t ntau, int force_waves, int for
   int T = force_slots > 0 ? force_slots : (int)((ntau + 64 * W - 1) / (64 * W));
   T = (T + 3) / 4 * 4;
   if (T < 4) T = 4;
-  if (T > 16 || (int64_t)64 * W * T < ntau) return sh;  // waves == 0: unsupported
+  if (T > 16) T = T <= 24 ? 24 : 32;
+  if (T > 32 || (int64_t)64 * W * T < ntau) return sh;  // waves == 0: unsupported
   sh.waves = W;
   sh.slots = T;
   const int NV = kB * nsrc;
   const int npad = W * 64 * T;
-  sh.lds = sizeof(double) * ((size_t)2 * npad + (size_t)W * NV * 16 + 2 * (size_t)W * NV) +
+  sh.lds = sizeof(double) * ((size_t)2 * npad + (size_t)(npad + 1) / 2 + (size_t)W * NV * 16 +
+                            2 * (size_t)W * NV) +
            4 * sizeof(int);
   return sh;
 }
