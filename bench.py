@@ -1,11 +1,15 @@
-"""Benchmark: LOS projection + C_l on one MI355X (FP64 plain path).
+"""Benchmark: LOS projection + C_l on one MI355X.
 
 One step = los_project (Eq. 2-3) + cl_integrate (Eq. 1) for one model of the
-benchmark workload (default C2: T/E/lensing sources, l = 2..2500, 4000 log-k
-on [1e-4, 0.5], 3000 tau on [0, 14000]; outputs TT, EE, TE, phi-phi), with all
-inputs resident in HBM.  Prints ONE JSON line.
+benchmark workload (default C2, FP64: T/E/lensing sources, l = 2..2500, 4000
+log-k on [1e-4, 0.5], 3000 tau on [0, 14000]; outputs TT, EE, TE, phi-phi),
+with all inputs resident in HBM.  Prints ONE JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--config C2] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--config C2] [--prec fp64|fp32|bf16x3]
+                  [--no-cpu-baseline]
+
+--config C3 --prec bf16x3 (or fp32) runs the mixed-precision workload (l up to
+5000, 8000 k, 4000 tau; S and Delta in FP32, j_l in FP64, C_l sum in FP64).
 """
 import argparse
 import json
@@ -21,7 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "C_ℓ spectra/s and Δ_ℓ(k) GFMA/s vs FP64 plain path at ≤1e-4 rel err"
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_cl_oracle.txt")
+GOLDEN = {"C2": os.path.join(ROOT, "tests", "golden", "c2_cl_oracle.txt"),
+          "C3": os.path.join(ROOT, "tests", "golden", "c3_cl_oracle.txt")}
+PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
 def tp_and_band_counts(wl):
@@ -40,6 +46,28 @@ def tp_and_band_counts(wl):
     return tp, band
 
 
+def traffic_for(prec, wl):
+    """HBM bytes per projection launch from the committed counter profile of the same kernel
+    source and workload (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    plain device copy of known size); None when there is none or the source has changed."""
+    import hashlib
+    if prec != 0:
+        return None
+    path = os.path.join(ROOT, "profiles", "project_fp64_%s.txt" % wl.name)
+    src = os.path.join(ROOT, "paper_2509_25110_amd", "csrc", "project_fp64.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#")):
+            key, val = line.split(":", 1)
+            fields[key.strip()] = val.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(wl, stride):
     import oracle
     rows = np.arange(0, wl.nk, stride)
@@ -56,9 +84,10 @@ def cpu_baseline(wl, stride):
 
 
 def golden_error(c, wl):
-    if wl.name != "C2" or not os.path.exists(GOLDEN):
+    path = GOLDEN.get(wl.name)
+    if path is None or not os.path.exists(path):
         return None
-    g = np.loadtxt(GOLDEN)
+    g = np.loadtxt(path)
     ls = g[:, 0].astype(int) - wl.lmin
     worst = 0.0
     for p, (a, b) in enumerate(wl.pairs):
@@ -78,8 +107,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C2")
+    ap.add_argument("--prec", default="fp64", choices=list(PRECS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--cpu-stride", type=int, default=0,
+                    help="oracle sample: every n-th k row (default 4 for C2, 16 for C3)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -104,16 +135,18 @@ def main():
 
     torch.cuda.set_device(0)
     wl = inputs.config(args.config)
+    prec = PRECS[args.prec]
+    sdt = np.float64 if prec == 0 else np.float32
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
-    k, tau, w, S = dv(wl.k), dv(wl.tau), dv(wl.w_tau), dv(wl.S)
+    k, tau, w, S = dv(wl.k), dv(wl.tau), dv(wl.w_tau), dv(wl.S.astype(sdt))
     wk, Pk = dv(wl.w_lnk), dv(wl.Pk)
-    delta = torch.empty((wl.nk, wl.nl, wl.nsrc), dtype=torch.float64, device="cuda")
+    delta = torch.empty((wl.nk, wl.nl, wl.nsrc), dtype=S.dtype, device="cuda")
     cl = torch.empty((len(wl.pairs), wl.nl), dtype=torch.float64, device="cuda")
     ctx = los.Context()
     stream = torch.cuda.current_stream()
 
     def step():
-        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, delta=delta)
+        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
         ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
 
     torch.cuda.synchronize()
@@ -134,7 +167,7 @@ def main():
     start.record(stream)
     for i in range(K):
         ev[i][0].record(stream)
-        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, delta=delta)
+        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
         ev[i][1].record(stream)
         ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
     end.record(stream)
@@ -150,6 +183,8 @@ def main():
     gfma = wl.nsrc * tp / (ms_per_step * 1e-3) / 1e9
     err = golden_error(cl.cpu().numpy(), wl)
 
+    path = {0: "FP64 plain path", 1: "FP32 MFMA path", 2: "split-BF16x3 MFMA path"}[prec]
+    kernel = "project_fp64_kernel" if prec == 0 else "jtable_kernel + mfma_gemm_kernel"
     out = {
         "metric": METRIC,
         "value": K / (total_ms * 1e-3),
@@ -161,14 +196,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {0: "f64", 1: "f64 j_l, f32 product", 2: "f64 j_l, bf16x3 product"}[prec],
         "data": "synthetic",
-        "config": {"workload": "%s: %s, FP64 plain path" % (wl.name, inputs.DESCRIPTIONS[wl.name]),
+        "config": {"workload": "%s: %s, %s" % (wl.name, inputs.DESCRIPTIONS[wl.name], path),
                    "nk": wl.nk, "ntau": wl.ntau, "lmax": wl.lmax, "nsrc": wl.nsrc,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "project_fp64_kernel", "kernel_ms": proj_ms,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic_for(prec, wl),
+                     "kernel": kernel, "kernel_ms": proj_ms,
                      "work": "%d TP (l,k,tau) entries x %d FP64 flops" % (tp, 3 + 2 * wl.nsrc)},
         "gfma_per_s": gfma,
         "tp_entries": tp,
@@ -179,7 +215,8 @@ def main():
         "max_rel_err_vs_oracle": err,
     }
     if not args.no_cpu_baseline and rank == 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_stride)
+        stride = args.cpu_stride or {"C3": 16}.get(wl.name, 4)
+        out["cpu_baseline"] = cpu_baseline(wl, stride)
     ctx.close()
     if rank == 0:
         print(json.dumps(out), flush=True)

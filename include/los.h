@@ -55,8 +55,9 @@ typedef enum {
 
 typedef enum {
     LOS_FP64 = 0,   /* IEEE double throughout                                 */
-    LOS_FP32 = 1,   /* reserved: FP32 projection GEMM on MFMA, FP64 j_l       */
-    LOS_BF16X3 = 2  /* reserved: split-BF16x3 projection GEMM on MFMA         */
+    LOS_FP32 = 1,   /* FP64 j_l rounded to FP32; FP32 MFMA product, FP32 sum  */
+    LOS_BF16X3 = 2  /* FP64 j_l rounded to FP32, split into bf16 hi + lo;
+                       three bf16 MFMA products, FP32 sum                      */
 } los_prec;
 
 typedef struct los_ctx los_ctx;
@@ -106,11 +107,21 @@ int los_bessel_table(los_ctx *ctx, const double *x, int64_t nx, int32_t lmin, in
  *
  * k: device, nk doubles (> 0).  tau, w_tau: device, ntau doubles, with
  * tau[n] <= tau0.  S: device, nsrc*nk*ntau values.  delta: device,
- * nk*nl*nsrc values.  For prec == LOS_FP64, S and delta are double.
+ * nk*nl*nsrc values.  For prec == LOS_FP64, S and delta are double; for
+ * LOS_FP32 and LOS_BF16X3 they are float.
  * Limits: 2 <= lmin <= lmax <= 16000, 1 <= nsrc <= 4, 1 <= ntau <= 8192,
- * nk >= 1.  Other precisions: LOS_ERR_UNSUPPORTED.
- * The j_l are generated on the fly (never stored); the band where
- * |j_l| < ~1e-21 of its peak is skipped.
+ * nk >= 1.
+ *
+ * LOS_FP64: the j_l are generated on the fly in registers (never stored) and
+ * the band where |j_l| < ~1e-21 of its peak is skipped.
+ * LOS_FP32 / LOS_BF16X3 (Sec. 2.1 Eq. 2-3 as the per-k matrix product
+ * Delta_k[l][s] = sum_n J_k[l][n] S[s][k][n], J_k[l][n] = w_n j_l(k chi_n)):
+ * the tables J_k are built in FP64 (downward recurrence from the band edge,
+ * upward recurrence for the seeds), rounded to FP32 and kept in a context
+ * workspace of at most LOS_JTAB_MIB MiB (environment, default 4096) for a
+ * chunk of k rows, then multiplied on the matrix cores with FP32
+ * accumulation.  Expected C_l error ~1e-6 relative (both precisions).
+ * Errors: LOS_ERR_OOM if the workspace cannot be allocated.
  */
 int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
                 const double *k, const double *tau, const double *w_tau, const void *S,

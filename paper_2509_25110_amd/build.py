@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblos.so")
 
-SOURCES = ["los_api.cpp", "bessel_table.hip", "project_fp64.hip", "cl_reduce.hip"]
+SOURCES = ["los_api.cpp", "bessel_table.hip", "project_fp64.hip", "cl_reduce.hip", "jtable.hip",
+           "project_mfma.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -30,8 +31,18 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC]
 
 
-def _compile(src: str) -> str:
+def _headers():
+    hs = [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    hs += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    return hs
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        newest = max(os.path.getmtime(p) for p in _headers() + [os.path.join(CSRC, src)])
+        if os.path.getmtime(obj) > newest:
+            return obj
     cmd = [HIPCC, *CFLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -39,13 +50,14 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    """Compile all sources and link liblos.so; returns the library path."""
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compile all sources and link liblos.so; returns the library path.
+    incremental=True reuses objects newer than their source and every header."""
     if shutil.which(HIPCC) is None and not os.path.exists(HIPCC):
         raise RuntimeError("hipcc not found (%s)" % HIPCC)
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, incremental), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,5 +70,5 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -1,0 +1,134 @@
+// Weighted Bessel tables for the MFMA projection (gCAMB paper, Sec. 2.1
+// Eq. 2-3, written as a matrix product per k):
+//
+//   J_k[l][n] = w_n * j_l(k * (tau0 - tau_n)),   so   Delta_k = J_k . S_k
+//
+// One lane per tau node, one workgroup column per k.  Each lane first finds
+// a normalised pair (J_R, J_{R+1}) at its top row R = min(ltop(x), lmax):
+//   * x >= lmax + 1: upward recurrence from j_0 = sin x / x, j_{-1} = cos x / x
+//     (stable on the oscillatory side) up to l = lmax + 1;
+//   * otherwise: upward to m = floor(x) for j_m, and Miller's downward
+//     recurrence from ltop(x) with seeds (0, 1) down to m; the Miller values
+//     are scaled by j_m / J^_m.
+// It then runs the recurrence DOWNWARD from R to lmin, writing every row.
+// Downward is the stable direction above the turning point and neutrally
+// stable below it (both solutions oscillate with equal amplitude there), so
+// a single descending sweep covers the whole band.
+//
+// Output, FP32 (w folded in before rounding):
+//   J[(kc * nlp + (l - lmin)) * ntp + n]   rows padded to nlp = 16 * nlb,
+//                                           columns to ntp = 32 * ntb,
+// and top[kc * ntb + tb] = highest 16-row block holding a non-zero row in the
+// 32-node block tb (-1: none).  Blocks above `top` are not written; the
+// GEMM never reads them.
+#include "bessel_dev.hpp"
+#include "los_internal.hpp"
+
+namespace los {
+namespace {
+
+__device__ inline int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ inline int half_max_i(int v) {
+#pragma unroll
+  for (int o = 16; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
+  const int ki = blockIdx.y;
+  const int64_t i = a.k0 + ki;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  if ((int64_t)blockIdx.x * 256 + (threadIdx.x & ~63) >= a.ntp) return;  // whole wave is padding
+
+  int R = -1;
+  double ix = 0.0, cur = 0.0, nxt = 0.0;
+  if (n < a.ntau) {
+    const double chi = a.tau0 - a.tau[n];
+    const double x = a.k[i] * chi;
+    const double wt = a.w[n];
+    if (x >= kXTiny && wt != 0.0) {
+      ix = 1.0 / x;
+      const int m = (int)x;
+      const int L0 = ltop_of(x);
+      double s, c;
+      sincos(x, &s, &c);
+      double p = c * ix, q = s * ix;  // j_{l-1}, j_l at l = 0
+      if (m >= a.lmax + 1) {
+        for (int l = 0; l <= a.lmax; ++l) {
+          const double r = rec_step((double)(2 * l + 1) * ix, q, p);
+          p = q;
+          q = r;
+        }
+        R = a.lmax;
+        cur = wt * p;
+        nxt = wt * q;
+      } else {
+        for (int l = 0; l < m; ++l) {
+          const double r = rec_step((double)(2 * l + 1) * ix, q, p);
+          p = q;
+          q = r;
+        }
+        const double jm = q;
+        R = min(L0, a.lmax);
+        double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l at l = L0
+        double hR = 1.0, hR1 = 0.0;
+        for (int l = L0; l > m; --l) {
+          const double hp = rec_step((double)(2 * l + 1) * ix, hc, hn);
+          hn = hc;
+          hc = hp;
+          if (l - 1 == R) {
+            hR = hc;
+            hR1 = hn;
+          }
+        }
+        const double sc = wt * jm / hc;
+        cur = sc * hR;
+        nxt = sc * hR1;
+      }
+      if (R < a.lmin) R = -1;
+    }
+  }
+
+  const int tb_lane = R >= 0 ? (R - a.lmin) >> 4 : -1;
+  const int tb_half = half_max_i(tb_lane);
+  const int tb_wave = wave_max_i(tb_lane);
+  if ((lane & 31) == 0) {
+    const int64_t blk = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
+    if (blk < a.ntb) a.top[(int64_t)ki * a.ntb + blk] = tb_half;
+  }
+
+  if (n >= a.ntp) return;  // no column of its own (after the shuffles above)
+  float *col = a.J + (int64_t)ki * a.nlp * a.ntp + n;
+  for (int b = tb_wave; b >= 0; --b) {
+    const int lbase = a.lmin + 16 * b;
+    float *dst = col + (int64_t)(16 * b) * a.ntp;
+#pragma unroll
+    for (int r = 15; r >= 0; --r) {
+      const int l = lbase + r;
+      float v = 0.f;
+      if (l <= R) {
+        v = (float)cur;
+        const double pv = rec_step((double)(2 * l + 1) * ix, cur, nxt);
+        nxt = cur;
+        cur = pv;
+      }
+      dst[(int64_t)r * a.ntp] = v;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t jtable_launch(const JTableArgs &a, int kcount, hipStream_t s) {
+  dim3 grid((unsigned)((a.ntp + 255) / 256), (unsigned)kcount);
+  hipLaunchKernelGGL(jtable_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace los

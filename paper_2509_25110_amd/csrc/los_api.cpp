@@ -12,10 +12,15 @@
 
 #include "los_internal.hpp"
 
+// Workspace slots of a context: the C_l partial sums and the Bessel tables
+// of the MFMA projection live in separate buffers, so a C_l call queued
+// behind a projection never reallocates memory the projection still reads.
+enum { WS_CL = 0, WS_JTAB = 1, WS_COUNT = 2 };
+
 struct los_ctx {
   int device = 0;
-  void *ws = nullptr;
-  size_t ws_bytes = 0;
+  void *ws[WS_COUNT] = {};
+  size_t ws_bytes[WS_COUNT] = {};
 };
 
 namespace {
@@ -41,33 +46,120 @@ int hip_fail(hipError_t e, const char *what) {
   return fail(LOS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Grow the context workspace to at least `bytes` (never shrinks).
-int ws_reserve(los_ctx *ctx, size_t bytes, void **out) {
-  if (bytes <= ctx->ws_bytes) {
-    *out = ctx->ws;
+// Grow workspace slot `slot` of the context to at least `bytes` (never
+// shrinks).  hipFree waits for the device, so queued work that still uses the
+// old buffer finishes first.
+int ws_reserve(los_ctx *ctx, int slot, size_t bytes, void **out) {
+  if (bytes <= ctx->ws_bytes[slot]) {
+    *out = ctx->ws[slot];
     return LOS_OK;
   }
-  if (ctx->ws) {
-    hipError_t e = hipFree(ctx->ws);
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
+  if (ctx->ws[slot]) {
+    hipError_t e = hipFree(ctx->ws[slot]);
+    ctx->ws[slot] = nullptr;
+    ctx->ws_bytes[slot] = 0;
     if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
   }
   size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
-  hipError_t e = hipMalloc(&ctx->ws, want);
+  hipError_t e = hipMalloc(&ctx->ws[slot], want);
   if (e != hipSuccess) {
-    ctx->ws = nullptr;
+    ctx->ws[slot] = nullptr;
     return fail(LOS_ERR_OOM, "workspace allocation of %zu bytes failed: %s", want,
                 hipGetErrorString(e));
   }
-  ctx->ws_bytes = want;
-  *out = ctx->ws;
+  ctx->ws_bytes[slot] = want;
+  *out = ctx->ws[slot];
   return LOS_OK;
 }
 
 int env_int(const char *name) {
   const char *v = std::getenv(name);
   return v ? std::atoi(v) : 0;
+}
+
+// Bytes of Bessel table per k row for the MFMA projection.
+size_t jtab_bytes_per_k(int64_t nlp, int64_t ntp, int ntb) {
+  return sizeof(float) * (size_t)nlp * (size_t)ntp + sizeof(int) * (size_t)ntb;
+}
+
+// Number of k rows per Bessel-table chunk: LOS_JTAB_MIB (default 4096 MiB)
+// bounds the table workspace.
+int64_t jtab_chunk(int64_t nk, size_t per_k) {
+  int64_t mib = env_int("LOS_JTAB_MIB");
+  if (mib <= 0) mib = 4096;
+  int64_t kc = (int64_t)((size_t)mib * (1u << 20) / per_k);
+  if (kc < 1) kc = 1;
+  if (kc > nk) kc = nk;
+  if (kc > 65535) kc = 65535;
+  return kc;
+}
+
+los::GemmTile gemm_tile_for(int max_ncol) {
+  los::GemmTile t{env_int("LOS_GEMM_MB"), env_int("LOS_GEMM_NC")};
+  if (t.mb > 0 && t.nc > 0 && los::gemm_tile_supported(t)) return t;
+  if (max_ncol <= 16) return {4, 1};
+  if (max_ncol <= 32) return {2, 2};
+  return {2, 4};
+}
+
+// Mixed-precision projection: FP64 Bessel tables (w folded in, rounded to
+// FP32) in chunks of k rows, each followed by the MFMA product with S.
+int project_mixed(los_ctx *ctx, int lmin, int lmax, int64_t nk, int64_t ntau, double tau0,
+                  const double *k, const double *tau, const double *w_tau, const float *S,
+                  int nsrc, int prec, float *delta, hipStream_t stream) {
+  const int nl = lmax - lmin + 1;
+  const int nlb = (nl + 15) / 16;
+  const int ntb = (int)((ntau + 31) / 32);
+  const int64_t nlp = 16 * (int64_t)nlb, ntp = 32 * (int64_t)ntb;
+  const size_t per_k = jtab_bytes_per_k(nlp, ntp, ntb);
+  const int64_t kc = jtab_chunk(nk, per_k);
+  void *ws = nullptr;
+  int rc = ws_reserve(ctx, WS_JTAB, per_k * (size_t)kc, &ws);
+  if (rc != LOS_OK) return rc;
+  float *J = (float *)ws;
+  int *top = (int *)((char *)ws + sizeof(float) * (size_t)nlp * (size_t)ntp * (size_t)kc);
+
+  los::JTableArgs ja{};
+  ja.lmin = lmin;
+  ja.lmax = lmax;
+  ja.nlb = nlb;
+  ja.ntb = ntb;
+  ja.nlp = nlp;
+  ja.ntp = ntp;
+  ja.ntau = ntau;
+  ja.tau0 = tau0;
+  ja.k = k;
+  ja.tau = tau;
+  ja.w = w_tau;
+  ja.J = J;
+  ja.top = top;
+
+  los::GemmArgs ga{};
+  ga.nl = nl;
+  ga.nlb = nlb;
+  ga.ntb = ntb;
+  ga.nlp = nlp;
+  ga.ntp = ntp;
+  ga.ntau = ntau;
+  ga.J = J;
+  ga.top = top;
+  ga.S = S;
+  ga.s_kstride = ntau;
+  ga.s_cstride = nk * ntau;
+  ga.ncol = nsrc;
+  ga.delta = delta;
+  const los::GemmTile tile = gemm_tile_for(nsrc);
+
+  for (int64_t k0 = 0; k0 < nk; k0 += kc) {
+    const int cnt = (int)(nk - k0 < kc ? nk - k0 : kc);
+    ja.k0 = k0;
+    ga.k0 = k0;
+    hipError_t e = los::jtable_launch(ja, cnt, stream);
+    if (e != hipSuccess) return hip_fail(e, "los_project: Bessel table launch");
+    e = los::mfma_gemm_launch(ga, prec, tile, cnt, nsrc, stream);
+    if (e != hipSuccess) return hip_fail(e, "los_project: MFMA product launch");
+  }
+  return ok();
 }
 
 }  // namespace
@@ -93,7 +185,8 @@ int los_ctx_create(los_ctx **ctx) {
 
 void los_ctx_destroy(los_ctx *ctx) {
   if (!ctx) return;
-  if (ctx->ws) (void)hipFree(ctx->ws);
+  for (int i = 0; i < WS_COUNT; ++i)
+    if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   delete ctx;
 }
 
@@ -131,7 +224,8 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
   if (prec != LOS_FP64 && prec != LOS_FP32 && prec != LOS_BF16X3)
     return fail(LOS_ERR_INVALID, "los_project: unknown precision %d", prec);
   if (prec != LOS_FP64)
-    return fail(LOS_ERR_UNSUPPORTED, "los_project: precision %d is not implemented", prec);
+    return project_mixed(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S, nsrc,
+                         prec, (float *)delta, (hipStream_t)stream);
 
   los::ProjectShape sh =
       los::project_fp64_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"), env_int("LOS_PROJ_SLOTS"));
@@ -191,7 +285,7 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
   a.cl = cl;
   a.nseg = los::cl_segments(nk, nl);
   void *ws = nullptr;
-  int rc = ws_reserve(ctx, sizeof(double) * (size_t)a.nseg * npairs * nl, &ws);
+  int rc = ws_reserve(ctx, WS_CL, sizeof(double) * (size_t)a.nseg * npairs * nl, &ws);
   if (rc != LOS_OK) return rc;
   a.partial = (double *)ws;
   hipError_t e = los::cl_launch(a, (hipStream_t)stream);

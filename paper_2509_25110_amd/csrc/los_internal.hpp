@@ -33,6 +33,47 @@ ProjectShape project_fp64_shape(int nsrc, int64_t ntau, int force_waves = 0, int
 hipError_t project_fp64_launch(const ProjectArgs &a, int nsrc, const ProjectShape &sh,
                                hipStream_t s);
 
+// Weighted Bessel tables for the MFMA projection (see jtable.hip):
+// J[(kc*nlp + l - lmin)*ntp + n] = w_n j_l(k[k0 + kc] (tau0 - tau_n)) in FP32,
+// top[kc*ntb + tb] = highest 16-row block with a non-zero row in node block tb.
+struct JTableArgs {
+  int lmin, lmax, nlb, ntb;
+  int64_t nlp, ntp, ntau;
+  int64_t k0;
+  double tau0;
+  const double *k, *tau, *w;
+  float *J;
+  int *top;
+};
+hipError_t jtable_launch(const JTableArgs &a, int kcount, hipStream_t s);
+
+// Per-k matrix product Delta_k = J_k . S_k on the matrix cores (see
+// project_mfma.hip).  Column c of k-row kc of S is the node vector
+//   S + sbase(kc) + c * s_cstride,  sbase = col_off ? col_off[kc] * s_cstride
+//                                                   : (k0 + kc) * s_kstride;
+// Delta[dbase(kc) + row * ncol(kc) + c],  dbase = col_off ? col_off[kc] * nl
+//                                                 : (k0 + kc) * nl * ncol.
+struct GemmArgs {
+  int nl, nlb, ntb;
+  int64_t nlp, ntp, ntau;
+  int64_t k0;
+  const float *J;
+  const int *top;
+  const float *S;
+  int64_t s_kstride, s_cstride;
+  int ncol;                  // columns per k when col_cnt == nullptr
+  const int *col_cnt;        // per k-row column counts (device) or nullptr
+  const int64_t *col_off;    // per k-row first column (device) or nullptr
+  float *delta;
+};
+struct GemmTile {
+  int mb;  // 16-row l blocks per wave
+  int nc;  // 16-column blocks per wave
+};
+bool gemm_tile_supported(const GemmTile &t);
+hipError_t mfma_gemm_launch(const GemmArgs &a, int prec, const GemmTile &t, int kcount,
+                            int max_ncol, hipStream_t s);
+
 // Bessel table out[(l-lmin)*nx + i] = j_l(x[i]).
 hipError_t bessel_table_launch(const double *x, int64_t nx, int lmin, int lmax, double *out,
                                hipStream_t s);

@@ -143,6 +143,9 @@ class Context:
                     delta: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         nsrc, nk, ntau = S.shape
         nl = lmax - lmin + 1
+        want = torch.float64 if prec == LOS_FP64 else torch.float32
+        if S.dtype != want:
+            raise ValueError("S must be %s for precision %d (got %s)" % (want, prec, S.dtype))
         if delta is None:
             delta = torch.empty((nk, nl, nsrc), dtype=S.dtype, device=S.device)
         _need(k, torch.float64, nk, "k")

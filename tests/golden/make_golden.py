@@ -1,9 +1,11 @@
-"""Write the oracle's C_l for the full-size T/E/lensing workload (l = 2..2500,
-4000 log-k on [1e-4, 0.5], 3000 tau) at sampled multipoles.
+"""Write the oracle's C_l for a full-size T/E/lensing workload at sampled
+multipoles: C2 (l = 2..2500, 4000 log-k on [1e-4, 0.5], 3000 tau) or C3
+(l = 2..5000, 8000 log-k on [1e-4, 1], 4000 tau).
 
 Calls only the CPU oracle (and the seeded input generator).  Output:
-``c2_cl_oracle.txt`` with one line per sampled l: ``l TT EE TE PP`` (repr floats).
-Run from the repository root: ``python tests/golden/make_golden.py``.
+``c2_cl_oracle.txt`` / ``c3_cl_oracle.txt`` with one line per sampled l:
+``l TT EE TE PP`` (repr floats).
+Run from the repository root: ``python tests/golden/make_golden.py [C2|C3]``.
 """
 import os
 import sys
@@ -17,7 +19,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from paper_2509_25110_amd import inputs  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_cl_oracle.txt")
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def sampled_ells(lmin, lmax):
@@ -27,21 +29,22 @@ def sampled_ells(lmin, lmax):
     return sorted(ls)
 
 
-def main():
-    w = inputs.config("C2")
+def main(name="C2"):
+    out = os.path.join(HERE, "%s_cl_oracle.txt" % name.lower())
+    w = inputs.config(name)
     t = time.time()
     d = oracle.project(w.lmin, w.lmax, w.k, w.tau, w.tau0, w.w_tau, w.S)
     c = oracle.cl(d, w.w_lnk, w.Pk, w.pairs)
     ls = sampled_ells(w.lmin, w.lmax)
-    with open(OUT, "w") as f:
-        f.write("# oracle C_l, workload C2 (%s); columns: l %s\n"
-                % (inputs.DESCRIPTIONS["C2"], " ".join(w.pair_names)))
+    with open(out, "w") as f:
+        f.write("# oracle C_l, workload %s (%s); columns: l %s\n"
+                % (name, inputs.DESCRIPTIONS[name], " ".join(w.pair_names)))
         f.write("# written by tests/golden/make_golden.py with %d oracle threads in %.0f s\n"
                 % (oracle.num_threads(), time.time() - t))
         for l in ls:
             f.write("%d %s\n" % (l, " ".join(repr(float(v)) for v in c[:, l - w.lmin])))
-    print("wrote", OUT, len(ls), "rows")
+    print("wrote", out, len(ls), "rows")
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "C2")

@@ -86,16 +86,6 @@ def test_project_argument_validation(lib):
     assert rc == 1 and b"NULL" in lib.los_last_error()
 
 
-def test_unsupported_precision_reported(lib):
-    import torch
-    if torch.cuda.device_count() > 0:
-        pytest.skip("uses a dummy context and pointers; only run where nothing can launch")
-    ctx, _keep = _dummy_ctx()
-    p = ctypes.c_void_p(16)
-    rc = lib.los_project(ctx, 2, 10, 4, 8, 1.0, p, p, p, p, 1, 2, p, None)
-    assert rc == 4 and b"not implemented" in lib.los_last_error()
-
-
 def test_cl_and_table_validation(lib):
     ctx, _keep = _dummy_ctx()
     p = ctypes.c_void_p(16)
