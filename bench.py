@@ -101,6 +101,165 @@ def golden_error(c, wl):
     return worst
 
 
+PEAK = {"fp32_mfma": 157.3, "bf16x3_mfma": 2516.6 / 3.0}
+GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_cl_oracle.txt")
+
+
+def batch_tp_counts(b):
+    """Sum over models of their TP entries (l <= lmax_m with x = k chi >= l + 1/2) and of their
+    dense entries nk_m * ntau * (lmax_m - 1): host-side counting only."""
+    chi = b.tau0 - b.tau                       # decreasing in n
+    tp = 0
+    rows = np.unique(b.k_index)
+    t = np.floor(b.k_master[rows, None] * chi[None, :] - 0.5)      # [rows, ntau], non-increasing
+    cum = np.concatenate([np.zeros((rows.size, 1)), np.cumsum(np.maximum(t - 1, 0), axis=1)], 1)
+    pos = np.searchsorted(rows, b.k_index)
+    for m in range(b.nmodels):
+        lo, hi = b.koff[m], b.koff[m + 1]
+        L = float(b.lmax[m])
+        r = pos[lo:hi]
+        c = np.sum(t[r] > L, axis=1)            # nodes above the l_max cap
+        tp += int(np.sum((L - 1) * c + cum[r, -1] - cum[r, c]))
+    dense = int(np.sum((b.koff[1:] - b.koff[:-1]) * b.ntau * (b.lmax.astype(np.int64) - 1)))
+    return tp, dense
+
+
+def golden_error_c4(cl, b):
+    if not os.path.exists(GOLDEN_C4):
+        return None
+    g = np.loadtxt(GOLDEN_C4)
+    worst = 0.0
+    for m in np.unique(g[:, 0]).astype(int):
+        gm = g[g[:, 0] == m]
+        ls = gm[:, 1].astype(int) - 2
+        ref = gm[:, 2:].T
+        got = cl[m][:, ls]
+        for p, (a, c) in enumerate(b.pairs):
+            if a == c:
+                rel = np.abs(got[p] / ref[p] - 1)
+            else:
+                rel = np.abs(got[p] - ref[p]) / np.sqrt(ref[b.pairs.index((a, a))] *
+                                                        ref[b.pairs.index((c, c))])
+            worst = max(worst, float(np.max(rel)))
+    return worst
+
+
+def run_batch(args):
+    """C4: 256 drawn models on the shared 8000-point master k grid, one graph launch per step."""
+    import torch
+    from paper_2509_25110_amd import inputs, los
+    torch.cuda.set_device(0)
+    prec = PRECS[args.prec if args.prec != "fp64" else "bf16x3"]
+    b = inputs.batch_inputs(inputs.draw_models(256))
+    ctx = los.Context()
+    plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                prec=prec)
+    col, ncols = plan.los_batch_columns()
+    S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
+    inputs.batch_sources_device(b, col, S, torch)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    km, tau, w, wk, Pk = dv(b.k_master), dv(b.tau), dv(b.w_tau), dv(b.w_lnk), dv(b.Pk)
+    cl = torch.empty((b.nmodels, 4, int(b.lmax.max()) - 1), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.los_batch_solve(b.tau0, km, tau, w, S, wk, Pk, cl=cl)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(max(args.warmup - 1, 0)):
+        step()
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for i in range(K):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    times = [a.elapsed_time(c) for a, c in ev]
+    ms = float(np.sum(times)) / K
+    err = golden_error_c4(cl.cpu().numpy(), b)
+    tp, dense = batch_tp_counts(b)
+    flops = 2.0 * 3 * tp
+    peak = PEAK["bf16x3_mfma" if prec == 2 else "fp32_mfma"]
+    achieved = flops / (ms * 1e-3) / 1e12
+    info = plan.los_batch_info()
+    out = {
+        "metric": METRIC,
+        "value": b.nmodels / (ms * 1e-3),
+        "unit": "spectra/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {1: "f64 j_l, f32 product", 2: "f64 j_l, bf16x3 product"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "C4: %s, shared master k grid, %s MFMA, one graph launch per step"
+                               % (inputs.DESCRIPTIONS["C4"], args.prec if prec != 2 else "bf16x3"),
+                   "models": b.nmodels, "packed_columns": ncols, "master_rows": info["rows"],
+                   "ntau": b.ntau, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "whole batch solve (jtable + mfma_gemm + batch_cl, graph)",
+                     "kernel_ms": ms,
+                     "work": "2 x 3 sources x %d TP entries (useful FP32-equivalent flops)" % tp,
+                     "peak_note": "bf16x3: 2516.6 TF dense bf16 / 3" if prec == 2 else
+                                  "dense FP32 MFMA"},
+        "gfma_per_s": 3 * tp / (ms * 1e-3) / 1e9,
+        "tp_entries": tp, "dense_entries": dense,
+        "first_call_ms": first_ms, "wall_s_timed": wall,
+        "tile": [info["tile_mb"], info["tile_nc"]], "chunks": info["chunks"],
+        "max_rel_err_vs_oracle": err,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        m = 3
+        d = b.draws[m]
+        wlm = inputs.model_workload(d)
+        rows = np.arange(0, wlm.nk, 32)
+        Sm = np.ascontiguousarray(wlm.S[:, rows, :])
+        t0 = time.perf_counter()
+        oracle.project(wlm.lmin, wlm.lmax, wlm.k[rows], wlm.tau, wlm.tau0, wlm.w_tau, Sm)
+        dt = time.perf_counter() - t0
+        rate = rows.size * wlm.ntau * (wlm.lmax - 1) / dt      # dense entries per second
+        total = dense / rate
+        out["cpu_baseline"] = {"value": b.nmodels / total, "unit": "spectra/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "model %d, every 32nd of its %d k rows, all l and tau: "
+                                         "%.1f s; scaled by the batch's dense (k, tau, l) count"
+                                         % (m, wlm.nk, dt)}
+    if args.fp64_compare:
+        # the FP64 plain path on a few models of the batch, scaled by their share of TP work
+        sample = [0, 3, 100, 200]
+        tsum = 0.0
+        for i in sample:
+            wlm = inputs.model_workload(b.draws[i])
+            args64 = [dv(wlm.k), dv(wlm.tau), wlm.tau0, dv(wlm.w_tau), dv(wlm.S)]
+            ctx.los_project(wlm.lmin, wlm.lmax, args64[0], args64[1], args64[2], args64[3],
+                            args64[4])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dd = ctx.los_project(wlm.lmin, wlm.lmax, args64[0], args64[1], args64[2], args64[3],
+                                 args64[4])
+            ctx.cl_integrate(dd, dv(wlm.w_lnk), dv(wlm.Pk), wlm.pairs)
+            torch.cuda.synchronize()
+            tsum += time.perf_counter() - t0
+            del dd
+        tp_sub, _ = batch_tp_counts(inputs.batch_inputs([b.draws[i] for i in sample]))
+        out["fp64_plain_path"] = {"value": b.nmodels / (tsum * tp / tp_sub), "unit": "spectra/s",
+                                  "sample": "models %s solved one by one with the FP64 path "
+                                            "(%.3f s), scaled by TP work" % (sample, tsum)}
+    plan.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +270,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle sample: every n-th k row (default 4 for C2, 16 for C3)")
+    ap.add_argument("--fp64-compare", action="store_true",
+                    help="C4: also time the FP64 plain path on a sample of the batch's models")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -129,6 +290,8 @@ def main():
               "DESIGN.md); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.config == "C4":
+        return run_batch(args)
 
     import torch
     from paper_2509_25110_amd import inputs, los

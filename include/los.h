@@ -144,6 +144,60 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
                  int64_t nk, const double *w_lnk, const double *Pk, const int32_t *pairs,
                  int32_t npairs, double *cl, void *stream);
 
+/*
+ * Batched solve (Sec. 3.2 / Algorithm 1: the projection is independent per k;
+ * Eq. 2-3 and Eq. 1 per model).  nmodels models share one master k grid and
+ * one tau grid; model m uses master rows k_index[koff[m] .. koff[m+1]-1]
+ * (strictly increasing) and multipoles l = 2..lmax[m].  For every master row,
+ * the sources of all models that use it form the columns of one matrix
+ * product J_k . S_k (J_k built once, FP64 then FP32), computed on the matrix
+ * cores in `prec` (LOS_FP32 or LOS_BF16X3), and each model's C_l are summed
+ * over its own k in FP64.
+ *
+ * los_batch_create (host arrays; allocates the plan's device tables and a
+ * workspace of at most LOS_JTAB_MIB MiB of Bessel tables plus one chunk of
+ * products): lmax[nmodels] in [2, 16000]; koff[nmodels+1] with koff[0] = 0
+ * and koff[m+1] > koff[m]; k_index[koff[nmodels]] in [0, nk_master);
+ * pairs[2*npairs] source indices (1 <= npairs <= 16, 1 <= nsrc <= 4);
+ * 1 <= ntau <= 8192.  *plan receives a handle released by los_batch_destroy.
+ *
+ * los_batch_columns (host): col[koff[nmodels]] receives, for every (model m,
+ * position j), the packed column p = col[koff[m] + j] of its source 0; source
+ * s is column p + s.  *ncols receives the number of packed columns.  The
+ * caller stores S_packed[p * ntau + n] = S_s of model m at (k_index[koff[m]+j],
+ * tau_n), float.
+ *
+ * los_batch_solve (device arrays; enqueued on `stream`):
+ *   k_master[nk_master], tau[ntau], w_tau[ntau] (double);
+ *   S_packed[ncols * ntau] (float);
+ *   w_lnk[koff[nmodels]], Pk[koff[nmodels]] (double): model m's ln k
+ *     quadrature weights and primordial spectrum at its own k, position
+ *     koff[m] + j;
+ *   cl[nmodels * npairs * (L - 1)] (double, written), L = max lmax:
+ *     cl[(m * npairs + p) * (L - 1) + l - 2] = 4 pi sum_j w P Delta^a Delta^b,
+ *     zero for l > lmax[m].
+ * The first call times every compiled tile shape on the first chunk and keeps
+ * the fastest; each new set of argument pointers is captured once into a HIP
+ * graph that later calls replay.  A plan is not thread-safe.
+ * los_batch_info (host): info[8] = {tile l blocks, tile column blocks, rows
+ * per chunk, chunks, used master rows, max lmax, tuned, graph captured}.
+ */
+typedef struct los_batch los_batch;
+
+int los_batch_create(los_ctx *ctx, int32_t nmodels, int32_t nsrc, const int32_t *lmax,
+                     const int64_t *koff, const int64_t *k_index, int64_t nk_master, int64_t ntau,
+                     const int32_t *pairs, int32_t npairs, int32_t prec, los_batch **plan);
+
+int los_batch_columns(const los_batch *plan, int64_t *col, int64_t *ncols);
+
+int los_batch_info(const los_batch *plan, int32_t *info);
+
+int los_batch_solve(los_batch *plan, double tau0, const double *k_master, const double *tau,
+                    const double *w_tau, const float *S_packed, const double *w_lnk,
+                    const double *Pk, double *cl, void *stream);
+
+void los_batch_destroy(los_batch *plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,465 @@
+// Batched solve: many models whose k grids are subsets of one shared master
+// grid (gCAMB paper, Sec. 3.2 / Algorithm 1: the work is independent per k;
+// Eq. 2-3 per k is then one matrix product J_k . S_k whose columns are the
+// sources of every model that uses k, so the Bessel table of k is built once
+// for all of them).
+//
+// Plan (host, once): master rows used by at least one model are compacted;
+// each row's columns are the (model, source) pairs that use it, ordered by
+// model l_max (largest first) so a 16-column block can stop at the l_max of
+// its first column.  Rows are processed in chunks that fit a bounded device
+// workspace: Bessel tables (jtable.hip) -> MFMA product with transposed
+// output (project_mfma.hip) -> per-model C_l accumulation (batch_cl.hip).
+// The first solve times every compiled tile shape on the first chunk and
+// keeps the fastest (autotuner); the whole launch sequence is then captured
+// once into a HIP graph per set of argument pointers and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "los.h"
+#include "los_internal.hpp"
+
+using los::fail;
+using los::hip_fail;
+using los::ok;
+
+struct los_batch {
+  int device = 0;
+  int nmodels = 0, nsrc = 0, npairs = 0, prec = 0;
+  int lmin = 2, lmax_g = 0, nl = 0, nlb = 0, ntb = 0;
+  int pa[16] = {}, pb[16] = {};
+  int64_t ntau = 0, nlp = 0, ntp = 0, nk_master = 0, ncols = 0, nrows = 0, npos = 0;
+  std::vector<int64_t> pos_col;      // host copy: packed column of (model, j)
+  std::vector<int64_t> chunk_row0;   // [nchunks + 1]
+  std::vector<int> chunk_maxcol;     // widest row in each chunk
+  int64_t kc = 0;
+  int nchunks = 0;
+  // device
+  int64_t *d_rows = nullptr, *d_col_off = nullptr, *d_pos_col = nullptr, *d_koff = nullptr,
+          *d_jr = nullptr;
+  int *d_col_cnt = nullptr, *d_col_lmax = nullptr, *d_lmax = nullptr;
+  float *J = nullptr, *D = nullptr;
+  int *top = nullptr;
+  std::vector<int64_t> chunk_col0;  // packed column at the start of each chunk
+  // tuning and graph
+  los::GemmTile tile{2, 4};
+  bool tuned = false;
+  float tune_ms[los::kGemmTileCount] = {};
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *key[9] = {};
+  double key_tau0 = 0.0;
+};
+
+namespace {
+
+int env_i(const char *name, int dflt) {
+  const char *v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+template <class T>
+int dev_copy(T **dst, const T *src, size_t n) {
+  hipError_t e = hipMalloc((void **)dst, sizeof(T) * (n ? n : 1));
+  if (e != hipSuccess) return fail(LOS_ERR_OOM, "batch plan: hipMalloc failed: %s", hipGetErrorString(e));
+  if (n) {
+    e = hipMemcpy(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch plan: hipMemcpy");
+  }
+  return LOS_OK;
+}
+
+void free_plan(los_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  // `top` lives inside the J allocation
+  void *ptrs[] = {b->d_rows, b->d_col_off, b->d_pos_col, b->d_koff, b->d_jr, b->d_col_cnt,
+                  b->d_col_lmax, b->d_lmax, b->J, b->D};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete b;
+}
+
+struct SolveArgs {
+  double tau0;
+  const double *k, *tau, *w;
+  const float *S;
+  const double *w_lnk, *Pk;
+  double *cl;
+};
+
+los::JTableArgs jargs(const los_batch *b, const SolveArgs &s, int64_t r0) {
+  los::JTableArgs a{};
+  a.lmin = b->lmin;
+  a.lmax = b->lmax_g;
+  a.nlb = b->nlb;
+  a.ntb = b->ntb;
+  a.nlp = b->nlp;
+  a.ntp = b->ntp;
+  a.ntau = b->ntau;
+  a.k0 = r0;
+  a.row_index = b->d_rows;
+  a.tau0 = s.tau0;
+  a.k = s.k;
+  a.tau = s.tau;
+  a.w = s.w;
+  a.J = b->J;
+  a.top = b->top;
+  return a;
+}
+
+los::GemmArgs gargs(const los_batch *b, const SolveArgs &s, int c) {
+  los::GemmArgs a{};
+  a.lmin = b->lmin;
+  a.nl = b->nl;
+  a.nlb = b->nlb;
+  a.ntb = b->ntb;
+  a.nlp = b->nlp;
+  a.ntp = b->ntp;
+  a.ntau = b->ntau;
+  a.k0 = b->chunk_row0[c];
+  a.J = b->J;
+  a.top = b->top;
+  a.S = s.S;
+  a.s_cstride = b->ntau;
+  a.col_cnt = b->d_col_cnt;
+  a.col_off = b->d_col_off;
+  a.col_base = b->chunk_col0[c];
+  a.col_lmax = b->d_col_lmax;
+  a.dtrans = 1;
+  a.delta = b->D;
+  return a;
+}
+
+// Enqueue the whole solve on stream st.
+int enqueue(los_batch *b, const SolveArgs &s, hipStream_t st) {
+  hipError_t e = los::fill_zero_launch(s.cl, (int64_t)b->nmodels * b->npairs * b->nl, st);
+  if (e != hipSuccess) return hip_fail(e, "los_batch_solve: fill launch");
+  for (int c = 0; c < b->nchunks; ++c) {
+    const int64_t r0 = b->chunk_row0[c];
+    const int cnt = (int)(b->chunk_row0[c + 1] - r0);
+    e = los::jtable_launch(jargs(b, s, r0), cnt, st);
+    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: Bessel table launch");
+    e = los::mfma_gemm_launch(gargs(b, s, c), b->prec, b->tile, cnt, b->chunk_maxcol[c], st);
+    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: MFMA product launch");
+    los::BatchClArgs ca{};
+    ca.nmodels = b->nmodels;
+    ca.nsrc = b->nsrc;
+    ca.npairs = b->npairs;
+    ca.lmin = b->lmin;
+    ca.nl = b->nl;
+    ca.chunk = c;
+    std::memcpy(ca.pa, b->pa, sizeof ca.pa);
+    std::memcpy(ca.pb, b->pb, sizeof ca.pb);
+    ca.lmax = b->d_lmax;
+    ca.koff = b->d_koff;
+    ca.jr = b->d_jr;
+    ca.pos_col = b->d_pos_col;
+    ca.col_base = b->chunk_col0[c];
+    ca.D = b->D;
+    ca.w_lnk = s.w_lnk;
+    ca.Pk = s.Pk;
+    ca.cl = s.cl;
+    e = los::batch_cl_launch(ca, st);
+    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: C_l launch");
+  }
+  return LOS_OK;
+}
+
+// Time every compiled tile shape on the first chunk (its Bessel table built
+// once); keep the fastest.  LOS_BATCH_TILE_MB / _NC pin a shape instead.
+int autotune(los_batch *b, const SolveArgs &s, hipStream_t st) {
+  const int mb = env_i("LOS_BATCH_TILE_MB", 0), nc = env_i("LOS_BATCH_TILE_NC", 0);
+  if (mb > 0 && nc > 0) {
+    los::GemmTile t{mb, nc};
+    if (!los::gemm_tile_supported(t))
+      return fail(LOS_ERR_INVALID, "los_batch_solve: tile %d x %d is not compiled", mb, nc);
+    b->tile = t;
+    b->tuned = true;
+    return LOS_OK;
+  }
+  if (!env_i("LOS_BATCH_TUNE", 1)) {
+    b->tuned = true;
+    return LOS_OK;
+  }
+  const int cnt = (int)(b->chunk_row0[1] - b->chunk_row0[0]);
+  hipError_t e = los::jtable_launch(jargs(b, s, b->chunk_row0[0]), cnt, st);
+  if (e != hipSuccess) return hip_fail(e, "autotune: Bessel table launch");
+  hipEvent_t t0, t1;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return hip_fail(e, "autotune: event");
+  if ((e = hipEventCreate(&t1)) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return hip_fail(e, "autotune: event");
+  }
+  float best = 1e30f;
+  int rc = LOS_OK;
+  for (int i = 0; i < los::kGemmTileCount && rc == LOS_OK; ++i) {
+    const los::GemmTile t = los::gemm_tile_at(i);
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && rc == LOS_OK; ++rep) {  // first run warms up
+      e = hipEventRecord(t0, st);
+      if (e == hipSuccess) e = los::mfma_gemm_launch(gargs(b, s, 0), b->prec, t, cnt,
+                                                      b->chunk_maxcol[0], st);
+      if (e == hipSuccess) e = hipEventRecord(t1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) rc = hip_fail(e, "autotune");
+    }
+    b->tune_ms[i] = ms;
+    if (rc == LOS_OK && ms < best) {
+      best = ms;
+      b->tile = t;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc == LOS_OK) b->tuned = true;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int los_batch_create(los_ctx *ctx, int32_t nmodels, int32_t nsrc, const int32_t *lmax,
+                     const int64_t *koff, const int64_t *k_index, int64_t nk_master, int64_t ntau,
+                     const int32_t *pairs, int32_t npairs, int32_t prec, los_batch **plan) {
+  if (!plan) return fail(LOS_ERR_INVALID, "los_batch_create: plan is NULL");
+  *plan = nullptr;
+  if (!ctx) return fail(LOS_ERR_INVALID, "los_batch_create: ctx is NULL");
+  if (nmodels < 1) return fail(LOS_ERR_INVALID, "los_batch_create: nmodels = %d", nmodels);
+  if (nsrc < 1 || nsrc > 4) return fail(LOS_ERR_INVALID, "los_batch_create: nsrc = %d", nsrc);
+  if (!lmax || !koff || !k_index || !pairs)
+    return fail(LOS_ERR_INVALID, "los_batch_create: NULL array");
+  if (npairs < 1 || npairs > 16)
+    return fail(LOS_ERR_INVALID, "los_batch_create: npairs = %d out of [1, 16]", npairs);
+  if (prec != LOS_FP32 && prec != LOS_BF16X3)
+    return fail(LOS_ERR_INVALID, "los_batch_create: prec must be LOS_FP32 or LOS_BF16X3");
+  if (nk_master < 1 || nk_master > ((int64_t)1 << 31) - 1)
+    return fail(LOS_ERR_INVALID, "los_batch_create: nk_master = %lld", (long long)nk_master);
+  if (ntau < 1 || ntau > 8192)
+    return fail(LOS_ERR_INVALID, "los_batch_create: ntau = %lld out of [1, 8192]", (long long)ntau);
+  for (int p = 0; p < npairs; ++p)
+    if (pairs[2 * p] < 0 || pairs[2 * p] >= nsrc || pairs[2 * p + 1] < 0 ||
+        pairs[2 * p + 1] >= nsrc)
+      return fail(LOS_ERR_INVALID, "los_batch_create: pair %d out of range", p);
+  if (koff[0] != 0) return fail(LOS_ERR_INVALID, "los_batch_create: koff[0] must be 0");
+  int lmax_g = 2;
+  for (int m = 0; m < nmodels; ++m) {
+    if (lmax[m] < 2 || lmax[m] > 16000)
+      return fail(LOS_ERR_INVALID, "los_batch_create: lmax[%d] = %d out of [2, 16000]", m, lmax[m]);
+    if (koff[m + 1] <= koff[m])
+      return fail(LOS_ERR_INVALID, "los_batch_create: model %d has no k", m);
+    for (int64_t p = koff[m]; p < koff[m + 1]; ++p) {
+      if (k_index[p] < 0 || k_index[p] >= nk_master)
+        return fail(LOS_ERR_INVALID, "los_batch_create: k_index[%lld] out of range", (long long)p);
+      if (p > koff[m] && k_index[p] <= k_index[p - 1])
+        return fail(LOS_ERR_INVALID, "los_batch_create: model %d k_index not increasing", m);
+    }
+    lmax_g = std::max(lmax_g, (int)lmax[m]);
+  }
+
+  los_batch *b = new (std::nothrow) los_batch;
+  if (!b) return fail(LOS_ERR_OOM, "los_batch_create: out of host memory");
+  (void)hipGetDevice(&b->device);
+  b->nmodels = nmodels;
+  b->nsrc = nsrc;
+  b->npairs = npairs;
+  b->prec = prec;
+  for (int p = 0; p < npairs; ++p) {
+    b->pa[p] = pairs[2 * p];
+    b->pb[p] = pairs[2 * p + 1];
+  }
+  b->lmax_g = lmax_g;
+  b->nl = lmax_g - b->lmin + 1;
+  b->nlb = (b->nl + 15) / 16;
+  b->nlp = 16 * (int64_t)b->nlb;
+  b->ntau = ntau;
+  b->ntb = (int)((ntau + 31) / 32);
+  b->ntp = 32 * (int64_t)b->ntb;
+  b->nk_master = nk_master;
+  b->npos = koff[nmodels];
+
+  // models per master row, each row ordered by l_max (largest first), then model index
+  std::vector<int> order(nmodels);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return lmax[x] > lmax[y]; });
+  std::vector<int64_t> users(nk_master + 1, 0);
+  for (int64_t p = 0; p < b->npos; ++p) users[k_index[p] + 1]++;
+  for (int64_t K = 0; K < nk_master; ++K) users[K + 1] += users[K];
+  std::vector<int> row_models(b->npos);
+  std::vector<int64_t> row_pos(b->npos);
+  {
+    std::vector<int64_t> fillp(users.begin(), users.end() - 1);
+    for (int oi = 0; oi < nmodels; ++oi) {
+      const int m = order[oi];
+      for (int64_t p = koff[m]; p < koff[m + 1]; ++p) {
+        const int64_t slot = fillp[k_index[p]]++;
+        row_models[slot] = m;
+        row_pos[slot] = p;
+      }
+    }
+  }
+  std::vector<int64_t> rows, col_off;
+  std::vector<int> col_cnt, col_lmax;
+  std::vector<int64_t> row_of_master(nk_master, -1);
+  b->pos_col.assign(b->npos, 0);
+  int64_t col = 0;
+  for (int64_t K = 0; K < nk_master; ++K) {
+    const int64_t u0 = users[K], u1 = users[K + 1];
+    if (u0 == u1) continue;
+    row_of_master[K] = (int64_t)rows.size();
+    rows.push_back(K);
+    col_off.push_back(col);
+    col_cnt.push_back((int)((u1 - u0) * nsrc));
+    for (int64_t u = u0; u < u1; ++u) {
+      b->pos_col[row_pos[u]] = col;
+      for (int s = 0; s < nsrc; ++s) col_lmax.push_back(lmax[row_models[u]]);
+      col += nsrc;
+    }
+  }
+  col_off.push_back(col);
+  b->ncols = col;
+  b->nrows = (int64_t)rows.size();
+
+  // chunks of rows: Bessel tables within LOS_JTAB_MIB (default 4096 MiB)
+  const size_t jrow = sizeof(float) * (size_t)b->nlp * b->ntp + sizeof(int) * b->ntb;
+  int64_t mib = env_i("LOS_JTAB_MIB", 4096);
+  if (mib < 1) mib = 1;
+  b->kc = std::max<int64_t>(1, std::min<int64_t>((int64_t)((size_t)mib * (1u << 20) / jrow), 65535));
+  b->kc = std::min(b->kc, b->nrows);
+  size_t dmax = 0;
+  for (int64_t r0 = 0; r0 < b->nrows; r0 += b->kc) {
+    const int64_t r1 = std::min(b->nrows, r0 + b->kc);
+    b->chunk_row0.push_back(r0);
+    b->chunk_col0.push_back(col_off[r0]);
+    int mc = 0;
+    for (int64_t r = r0; r < r1; ++r) mc = std::max(mc, col_cnt[r]);
+    b->chunk_maxcol.push_back(mc);
+    dmax = std::max(dmax, (size_t)(col_off[r1] - col_off[r0]) * b->nl);
+  }
+  b->chunk_row0.push_back(b->nrows);
+  b->nchunks = (int)b->chunk_row0.size() - 1;
+
+  // j range of every model in every chunk
+  std::vector<int64_t> jr((size_t)b->nchunks * nmodels * 2);
+  for (int m = 0; m < nmodels; ++m) {
+    int64_t j = 0;
+    const int64_t nkm = koff[m + 1] - koff[m];
+    for (int c = 0; c < b->nchunks; ++c) {
+      const int64_t jlo = j;
+      while (j < nkm && row_of_master[k_index[koff[m] + j]] < b->chunk_row0[c + 1]) ++j;
+      jr[((size_t)c * nmodels + m) * 2] = jlo;
+      jr[((size_t)c * nmodels + m) * 2 + 1] = j;
+    }
+  }
+
+  std::vector<int> lmax_v(lmax, lmax + nmodels);
+  std::vector<int64_t> koff_v(koff, koff + nmodels + 1);
+  int rc = LOS_OK;
+  if (rc == LOS_OK) rc = dev_copy(&b->d_rows, rows.data(), rows.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_col_off, col_off.data(), col_off.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_col_cnt, col_cnt.data(), col_cnt.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_col_lmax, col_lmax.data(), col_lmax.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_pos_col, b->pos_col.data(), b->pos_col.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_koff, koff_v.data(), koff_v.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_lmax, lmax_v.data(), lmax_v.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_jr, jr.data(), jr.size());
+  if (rc == LOS_OK) {
+    hipError_t e = hipMalloc((void **)&b->J, jrow * (size_t)b->kc);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->D, sizeof(float) * (dmax ? dmax : 1));
+    if (e != hipSuccess) rc = fail(LOS_ERR_OOM, "los_batch_create: workspace: %s", hipGetErrorString(e));
+    if (b->J)
+      b->top = (int *)((char *)b->J + sizeof(float) * (size_t)b->nlp * b->ntp * (size_t)b->kc);
+  }
+  if (rc == LOS_OK) {
+    hipError_t e = hipStreamCreate(&b->cap);
+    if (e != hipSuccess) rc = hip_fail(e, "los_batch_create: stream");
+  }
+  if (rc != LOS_OK) {
+    free_plan(b);
+    return rc;
+  }
+  *plan = b;
+  return ok();
+}
+
+int los_batch_columns(const los_batch *plan, int64_t *col, int64_t *ncols) {
+  if (!plan || !col || !ncols) return fail(LOS_ERR_INVALID, "los_batch_columns: NULL argument");
+  std::memcpy(col, plan->pos_col.data(), sizeof(int64_t) * plan->pos_col.size());
+  *ncols = plan->ncols;
+  return ok();
+}
+
+int los_batch_info(const los_batch *plan, int32_t *info) {
+  if (!plan || !info) return fail(LOS_ERR_INVALID, "los_batch_info: NULL argument");
+  info[0] = plan->tile.mb;
+  info[1] = plan->tile.nc;
+  info[2] = (int32_t)plan->kc;
+  info[3] = plan->nchunks;
+  info[4] = (int32_t)plan->nrows;
+  info[5] = plan->lmax_g;
+  info[6] = plan->tuned ? 1 : 0;
+  info[7] = plan->exec ? 1 : 0;
+  return ok();
+}
+
+int los_batch_solve(los_batch *plan, double tau0, const double *k_master, const double *tau,
+                    const double *w_tau, const float *S_packed, const double *w_lnk,
+                    const double *Pk, double *cl, void *stream) {
+  if (!plan) return fail(LOS_ERR_INVALID, "los_batch_solve: plan is NULL");
+  if (!k_master || !tau || !w_tau || !S_packed || !w_lnk || !Pk || !cl)
+    return fail(LOS_ERR_INVALID, "los_batch_solve: NULL array");
+  if (!(tau0 == tau0)) return fail(LOS_ERR_INVALID, "los_batch_solve: tau0 is NaN");
+  hipStream_t st = (hipStream_t)stream;
+  SolveArgs s{tau0, k_master, tau, w_tau, S_packed, w_lnk, Pk, cl};
+  if (!plan->tuned) {
+    int rc = autotune(plan, s, st);
+    if (rc != LOS_OK) return rc;
+  }
+  if (!env_i("LOS_BATCH_GRAPH", 1)) {
+    int rc = enqueue(plan, s, st);
+    return rc == LOS_OK ? ok() : rc;
+  }
+  const void *key[9] = {k_master, tau, w_tau, S_packed, w_lnk, Pk, cl, nullptr, nullptr};
+  const bool same = plan->exec && plan->key_tau0 == tau0 &&
+                    std::memcmp(key, plan->key, sizeof key) == 0;
+  if (!same) {
+    if (plan->exec) {
+      (void)hipGraphExecDestroy(plan->exec);
+      plan->exec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: begin capture");
+    int rc = enqueue(plan, s, plan->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(plan->cap, &g);
+    if (rc != LOS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: end capture");
+    e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      plan->exec = nullptr;
+      return hip_fail(e, "los_batch_solve: graph instantiate");
+    }
+    std::memcpy(plan->key, key, sizeof key);
+    plan->key_tau0 = tau0;
+  }
+  hipError_t e = hipGraphLaunch(plan->exec, st);
+  if (e != hipSuccess) return hip_fail(e, "los_batch_solve: graph launch");
+  return ok();
+}
+
+void los_batch_destroy(los_batch *plan) {
+  if (plan) free_plan(plan);
+}
+
+}  // extern "C"

@@ -41,7 +41,7 @@ __device__ inline int half_max_i(int v) {
 
 __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
   const int ki = blockIdx.y;
-  const int64_t i = a.k0 + ki;
+  const int64_t i = a.row_index ? a.row_index[a.k0 + ki] : a.k0 + ki;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   if ((int64_t)blockIdx.x * 256 + (threadIdx.x & ~63) >= a.ntp) return;  // whole wave is padding

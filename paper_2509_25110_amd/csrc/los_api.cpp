@@ -24,8 +24,10 @@ struct los_ctx {
 };
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace los {
 
 int fail(int code, const char *fmt, ...) {
   char buf[512];
@@ -45,6 +47,14 @@ int ok() {
 int hip_fail(hipError_t e, const char *what) {
   return fail(LOS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace los
+
+namespace {
+
+using los::fail;
+using los::hip_fail;
+using los::ok;
 
 // Grow workspace slot `slot` of the context to at least `bytes` (never
 // shrinks).  hipFree waits for the device, so queued work that still uses the
@@ -135,6 +145,7 @@ int project_mixed(los_ctx *ctx, int lmin, int lmax, int64_t nk, int64_t ntau, do
   ja.top = top;
 
   los::GemmArgs ga{};
+  ga.lmin = lmin;
   ga.nl = nl;
   ga.nlb = nlb;
   ga.ntb = ntb;

@@ -39,7 +39,8 @@ hipError_t project_fp64_launch(const ProjectArgs &a, int nsrc, const ProjectShap
 struct JTableArgs {
   int lmin, lmax, nlb, ntb;
   int64_t nlp, ntp, ntau;
-  int64_t k0;
+  int64_t k0;                 // first row of the chunk
+  const int64_t *row_index;   // rows -> index into k (device) or nullptr (identity)
   double tau0;
   const double *k, *tau, *w;
   float *J;
@@ -48,13 +49,16 @@ struct JTableArgs {
 hipError_t jtable_launch(const JTableArgs &a, int kcount, hipStream_t s);
 
 // Per-k matrix product Delta_k = J_k . S_k on the matrix cores (see
-// project_mfma.hip).  Column c of k-row kc of S is the node vector
-//   S + sbase(kc) + c * s_cstride,  sbase = col_off ? col_off[kc] * s_cstride
-//                                                   : (k0 + kc) * s_kstride;
-// Delta[dbase(kc) + row * ncol(kc) + c],  dbase = col_off ? col_off[kc] * nl
-//                                                 : (k0 + kc) * nl * ncol.
+// project_mfma.hip).  With r = k0 + kc (kc = row within the chunk), column c
+// of row r of S is the node vector
+//   S + sbase + c * s_cstride,  sbase = col_off ? col_off[r] * s_cstride : r * s_kstride,
+// and the result goes to
+//   delta[dbase + row * ncol + c]   (dtrans == 0)  or  delta[dbase + c * nl + row] (dtrans),
+//   dbase = col_off ? (col_off[r] - col_base) * nl : r * nl * ncol.
+// col_lmax (optional, per packed column, absolute l, non-increasing within a
+// row): blocks above the first column of a 16-column block are skipped.
 struct GemmArgs {
-  int nl, nlb, ntb;
+  int lmin, nl, nlb, ntb;
   int64_t nlp, ntp, ntau;
   int64_t k0;
   const float *J;
@@ -62,8 +66,11 @@ struct GemmArgs {
   const float *S;
   int64_t s_kstride, s_cstride;
   int ncol;                  // columns per k when col_cnt == nullptr
-  const int *col_cnt;        // per k-row column counts (device) or nullptr
-  const int64_t *col_off;    // per k-row first column (device) or nullptr
+  const int *col_cnt;        // per row column counts (device) or nullptr
+  const int64_t *col_off;    // per row first packed column (device) or nullptr
+  int64_t col_base;          // packed column that maps to delta offset 0
+  const int *col_lmax;       // per packed column l_max (device) or nullptr
+  int dtrans;
   float *delta;
 };
 struct GemmTile {
@@ -71,8 +78,33 @@ struct GemmTile {
   int nc;  // 16-column blocks per wave
 };
 bool gemm_tile_supported(const GemmTile &t);
+// Tile shapes the batch autotuner tries.
+constexpr int kGemmTileCount = 7;
+GemmTile gemm_tile_at(int i);
 hipError_t mfma_gemm_launch(const GemmArgs &a, int prec, const GemmTile &t, int kcount,
                             int max_ncol, hipStream_t s);
+
+// Per-model C_l of a batch, one chunk of master rows at a time (batch_cl.hip).
+// D is the chunk's transposed product: D[(packed column - col_base) * nl + l - lmin].
+struct BatchClArgs {
+  int nmodels, nsrc, npairs, lmin, nl, chunk;
+  int pa[16], pb[16];
+  const int *lmax;         // [nmodels]
+  const int64_t *koff;     // [nmodels + 1] first k position of each model
+  const int64_t *jr;       // [nchunks][nmodels][2] j range of each model in each chunk
+  const int64_t *pos_col;  // [koff[nmodels]] packed column of (model, j), source 0
+  int64_t col_base;
+  const float *D;
+  const double *w_lnk, *Pk;  // [koff[nmodels]]
+  double *cl;                // [nmodels][npairs][nl]
+};
+hipError_t fill_zero_launch(double *p, int64_t n, hipStream_t s);
+hipError_t batch_cl_launch(const BatchClArgs &a, hipStream_t s);
+
+// Error reporting shared by the C entry points (los_api.cpp).
+int fail(int code, const char *fmt, ...);
+int ok();
+int hip_fail(hipError_t e, const char *what);
 
 // Bessel table out[(l-lmin)*nx + i] = j_l(x[i]).
 hipError_t bessel_table_launch(const double *x, int64_t nx, int lmin, int lmax, double *out,

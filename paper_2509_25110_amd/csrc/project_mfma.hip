@@ -50,15 +50,20 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(GemmArgs a) {
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, r16 = lane & 15;
+  const int64_t r = a.k0 + ki;
   const int lb0 = (blockIdx.x * 4 + w) * MB;
   if (lb0 >= a.nlb) return;
-  const int ncol = a.col_cnt ? a.col_cnt[ki] : a.ncol;
+  const int ncol = a.col_cnt ? a.col_cnt[r] : a.ncol;
   const int cb0 = blockIdx.y * NC;
   if (cb0 * 16 >= ncol) return;
+  // last 16-row block any column of this wave needs
+  int lb_last = a.nlb - 1;
+  if (a.col_lmax) lb_last = min(lb_last, (a.col_lmax[a.col_off[r] + cb0 * 16] - a.lmin) >> 4);
+  if (lb0 > lb_last) return;
 
-  const int64_t sbase = a.col_off ? a.col_off[ki] * a.s_cstride : (a.k0 + ki) * a.s_kstride;
-  const int64_t dbase = a.col_off ? a.col_off[ki] * (int64_t)a.nl
-                                  : (a.k0 + ki) * (int64_t)a.nl * ncol;
+  const int64_t sbase = a.col_off ? a.col_off[r] * a.s_cstride : r * a.s_kstride;
+  const int64_t dbase = a.col_off ? (a.col_off[r] - a.col_base) * (int64_t)a.nl
+                                  : r * (int64_t)a.nl * ncol;
   const float *Jk = a.J + (int64_t)ki * a.nlp * a.ntp;
   const int *topk = a.top + (int64_t)ki * a.ntb;
 
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(GemmArgs a) {
     for (int j = 0; j < NC; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   for (int tb = 0; tb < a.ntb; ++tb) {
-    const int top = topk[tb];
+    const int top = min(topk[tb], lb_last);
     if (top < lb0) continue;
     const int nb = min(MB, top - lb0 + 1);
     const int n0 = tb * 32 + 8 * g;
@@ -129,7 +134,7 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(GemmArgs a) {
 
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
-    if (lb0 + i >= a.nlb) break;
+    if (lb0 + i > lb_last) break;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
       const int c = (cb0 + j) * 16 + r16;
@@ -137,7 +142,10 @@ __global__ __launch_bounds__(256) void mfma_gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (lb0 + i) * 16 + 4 * g + v;
-        if (row < a.nl) a.delta[dbase + (int64_t)row * ncol + c] = acc[i][j][v];
+        if (row < a.nl) {
+          const int64_t o = a.dtrans ? (int64_t)c * a.nl + row : (int64_t)row * ncol + c;
+          a.delta[dbase + o] = acc[i][j][v];
+        }
       }
     }
   }
@@ -167,6 +175,12 @@ hipError_t launch_p(const GemmArgs &a, const GemmTile &t, int kcount, int max_nc
 }
 
 }  // namespace
+
+GemmTile gemm_tile_at(int i) {
+  static const GemmTile tiles[kGemmTileCount] = {{1, 1}, {2, 1}, {4, 1}, {2, 2},
+                                                 {2, 4}, {4, 2}, {4, 4}};
+  return tiles[i];
+}
 
 bool gemm_tile_supported(const GemmTile &t) {
   switch (t.mb * 16 + t.nc) {

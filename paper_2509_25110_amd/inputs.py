@@ -137,6 +137,8 @@ DESCRIPTIONS = {
     "C1": "TT, l=2..300, 400 log-k on [1e-4,0.05], 600 tau on [0,14000]",
     "C2": "TT/EE/TE/PP, l=2..2500, 4000 log-k on [1e-4,0.5], 3000 tau on [0,14000]",
     "C3": "TT/EE/TE/PP, l=2..5000, 8000 log-k on [1e-4,1.0], 4000 tau on [0,14000]",
+    "C4": "256 drawn models, TT/EE/TE/PP, l_max in [1500,5000], 2000..8000 of the 8000 master "
+          "log-k on [1e-4,1.0], 3000 tau on [0,14000]",
 }
 
 
@@ -206,3 +208,78 @@ def model_workload(d: ModelDraw, ntau: int = 3000, master_nk: int = MASTER_NK,
                     pairs=PAIRS_4, pair_names=PAIR_NAMES_4,
                     params=dict(A_s=d.A_s, n_s=d.n_s, tau_star=d.tau_star, width=d.width,
                                 a_isw=d.a_isw))
+
+
+@dataclasses.dataclass
+class BatchInputs:
+    """A batch of drawn models on one shared master k grid (host arrays)."""
+    draws: List[ModelDraw]
+    k_master: np.ndarray   # [nk_master]
+    tau: np.ndarray        # [ntau]
+    tau0: float
+    w_tau: np.ndarray      # [ntau]
+    lmax: np.ndarray       # [nmodels] int32
+    koff: np.ndarray       # [nmodels + 1] int64
+    k_index: np.ndarray    # [koff[-1]] int64, master row of each (model, j)
+    w_lnk: np.ndarray      # [koff[-1]] each model's own ln k trapezoid weights
+    Pk: np.ndarray         # [koff[-1]] each model's A_s (k / k_pivot)^(n_s - 1)
+    pairs: Tuple[Tuple[int, int], ...] = PAIRS_4
+
+    @property
+    def nmodels(self) -> int:
+        return len(self.draws)
+
+    @property
+    def ntau(self) -> int:
+        return int(self.tau.size)
+
+
+def batch_inputs(draws: List[ModelDraw], ntau: int = 3000, master_nk: int = MASTER_NK,
+                 master_kmax: float = MASTER_KMAX, kmin: float = 1e-4) -> BatchInputs:
+    kmaster = log_k_grid(master_nk, kmin, master_kmax)
+    tau = tau_grid(ntau)
+    koff = [0]
+    idx, wl, pk = [], [], []
+    for d in draws:
+        i = master_indices(d.nk, master_nk)
+        k = kmaster[i]
+        idx.append(i)
+        wl.append(trapezoid_weights(np.log(k)))
+        pk.append(primordial(k, d.A_s, d.n_s))
+        koff.append(koff[-1] + i.size)
+    return BatchInputs(draws=list(draws), k_master=kmaster, tau=tau, tau0=TAU0,
+                       w_tau=trapezoid_weights(tau),
+                       lmax=np.array([d.lmax for d in draws], dtype=np.int32),
+                       koff=np.array(koff, dtype=np.int64), k_index=np.concatenate(idx),
+                       w_lnk=np.concatenate(wl), Pk=np.concatenate(pk))
+
+
+def batch_sources_host(b: BatchInputs, col: np.ndarray, ncols: int) -> np.ndarray:
+    """S_packed[ncols, ntau] float32: row col[koff[m] + j] + s holds source s of model m at its
+    j-th k (the layout a batch plan reports)."""
+    S = np.zeros((ncols, b.ntau), dtype=np.float32)
+    for m, d in enumerate(b.draws):
+        lo, hi = b.koff[m], b.koff[m + 1]
+        k = b.k_master[b.k_index[lo:hi]]
+        Sm = sources(k, b.tau, 3, tau_star=d.tau_star, width=d.width, a_isw=d.a_isw)
+        for s in range(3):
+            S[col[lo:hi] + s] = Sm[s]
+    return S
+
+
+def batch_sources_device(b: BatchInputs, col: np.ndarray, S_packed, torch) -> None:
+    """The same values as batch_sources_host, generated model by model on the device into the
+    float32 tensor S_packed[ncols, ntau] (the full 256-model batch does not fit host memory
+    comfortably).  Same formulas as `sources`, evaluated by torch in float64."""
+    dev = S_packed.device
+    tau = torch.from_numpy(b.tau).to(dev)
+    lens = torch.from_numpy(lensing_kernel(b.tau)).to(dev)
+    late = torch.exp(-((tau - 12000.0) ** 2) / (2.0 * 1500.0 ** 2))
+    for m, d in enumerate(b.draws):
+        lo, hi = int(b.koff[m]), int(b.koff[m + 1])
+        k = torch.from_numpy(b.k_master[b.k_index[lo:hi]]).to(dev)[:, None]
+        g = torch.exp(-((tau - d.tau_star) ** 2) / (2.0 * d.width * d.width))[None, :]
+        rows = torch.from_numpy(col[lo:hi]).to(dev)
+        S_packed[rows] = (g * (1.0 + 0.3 * torch.cos(150.0 * k)) + d.a_isw * late[None, :]).float()
+        S_packed[rows + 1] = (0.5 * k * k * g).float()
+        S_packed[rows + 2] = lens[None, :].expand(hi - lo, -1).float()

@@ -33,7 +33,8 @@ _STATUS = {1: "LOS_ERR_INVALID", 2: "LOS_ERR_HIP", 3: "LOS_ERR_OOM", 4: "LOS_ERR
 
 # every symbol include/los.h declares
 EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
-           "los_bessel_table", "los_project", "cl_integrate")
+           "los_bessel_table", "los_project", "cl_integrate", "los_batch_create",
+           "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_destroy")
 
 
 class LosError(RuntimeError):
@@ -63,6 +64,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cl_integrate.restype = ctypes.c_int
     lib.cl_integrate.argtypes = [vp, vp, i32, i32, i32, i64, vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
+    lib.los_batch_create.restype = ctypes.c_int
+    lib.los_batch_create.argtypes = [vp, i32, i32, vp, vp, vp, i64, i64, vp, i32, i32,
+                                     ctypes.POINTER(vp)]
+    lib.los_batch_columns.restype = ctypes.c_int
+    lib.los_batch_columns.argtypes = [vp, vp, ctypes.POINTER(i64)]
+    lib.los_batch_info.restype = ctypes.c_int
+    lib.los_batch_info.argtypes = [vp, vp]
+    lib.los_batch_solve.restype = ctypes.c_int
+    lib.los_batch_solve.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.los_batch_destroy.restype = None
+    lib.los_batch_destroy.argtypes = [vp]
     return lib
 
 
@@ -172,6 +184,87 @@ class Context:
         _check(lib().cl_integrate(self._h, _ptr(delta), prec, nsrc, nl, nk, _ptr(w_lnk), _ptr(Pk),
                                   arr, npairs, _ptr(cl), _stream(stream)))
         return cl
+
+
+    def los_batch_create(self, lmax, koff, k_index, nk_master: int, ntau: int,
+                         pairs: Sequence[Tuple[int, int]], prec: int = LOS_BF16X3,
+                         nsrc: int = 3) -> "Batch":
+        """Plan a batch (host arrays); see Batch."""
+        return Batch(self, lmax, koff, k_index, nk_master, ntau, pairs, prec, nsrc)
+
+
+class Batch:
+    """A los_batch plan: models on a shared master k grid (entry points los_batch_*)."""
+
+    def __init__(self, ctx: Context, lmax, koff, k_index, nk_master: int, ntau: int,
+                 pairs: Sequence[Tuple[int, int]], prec: int, nsrc: int):
+        import numpy as np
+        self._lmax = np.ascontiguousarray(lmax, dtype=np.int32)
+        self._koff = np.ascontiguousarray(koff, dtype=np.int64)
+        self._kidx = np.ascontiguousarray(k_index, dtype=np.int64)
+        flat = np.ascontiguousarray([int(v) for p in pairs for v in p], dtype=np.int32)
+        self.nmodels = int(self._lmax.size)
+        self.npairs = int(flat.size // 2)
+        self.nsrc = nsrc
+        self.ntau = int(ntau)
+        self.lmax_max = int(self._lmax.max())
+        h = ctypes.c_void_p()
+        _check(lib().los_batch_create(ctx.handle, self.nmodels, nsrc, self._lmax.ctypes.data,
+                                      self._koff.ctypes.data, self._kidx.ctypes.data,
+                                      int(nk_master), int(ntau), flat.ctypes.data, self.npairs,
+                                      prec, ctypes.byref(h)))
+        self._h = h
+
+    def los_batch_columns(self):
+        """(col, ncols): packed column of source 0 of every (model, j), and the column count."""
+        import numpy as np
+        col = np.zeros(int(self._koff[-1]), dtype=np.int64)
+        n = ctypes.c_int64()
+        _check(lib().los_batch_columns(self._h, col.ctypes.data, ctypes.byref(n)))
+        return col, int(n.value)
+
+    def los_batch_info(self) -> dict:
+        import numpy as np
+        info = np.zeros(8, dtype=np.int32)
+        _check(lib().los_batch_info(self._h, info.ctypes.data))
+        keys = ("tile_mb", "tile_nc", "rows_per_chunk", "chunks", "rows", "lmax", "tuned",
+                "graph")
+        return {k: int(v) for k, v in zip(keys, info)}
+
+    def los_batch_solve(self, tau0: float, k_master: torch.Tensor, tau: torch.Tensor,
+                        w_tau: torch.Tensor, S_packed: torch.Tensor, w_lnk: torch.Tensor,
+                        Pk: torch.Tensor, cl: Optional[torch.Tensor] = None,
+                        stream=None) -> torch.Tensor:
+        npos = int(self._koff[-1])
+        if cl is None:
+            cl = torch.empty((self.nmodels, self.npairs, self.lmax_max - 1), dtype=torch.float64,
+                             device=S_packed.device)
+        _need(tau, torch.float64, self.ntau, "tau")
+        _need(w_tau, torch.float64, self.ntau, "w_tau")
+        _need(w_lnk, torch.float64, npos, "w_lnk")
+        _need(Pk, torch.float64, npos, "Pk")
+        _need(cl, torch.float64, self.nmodels * self.npairs * (self.lmax_max - 1), "cl")
+        if S_packed.dtype != torch.float32 or S_packed.numel() % self.ntau:
+            raise ValueError("S_packed must be float32 [ncols, ntau]")
+        if k_master.dtype != torch.float64:
+            raise ValueError("k_master must be float64")
+        _check(lib().los_batch_solve(self._h, float(tau0), _ptr(k_master), _ptr(tau), _ptr(w_tau),
+                                     _ptr(S_packed), _ptr(w_lnk), _ptr(Pk), _ptr(cl),
+                                     _stream(stream)))
+        return cl
+
+    def los_batch_destroy(self):
+        if self._h is not None and self._h.value:
+            lib().los_batch_destroy(self._h)
+        self._h = None
+
+    close = los_batch_destroy
+
+    def __del__(self):
+        try:
+            self.los_batch_destroy()
+        except Exception:
+            pass
 
 
 def version() -> str:

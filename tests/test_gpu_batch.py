@@ -1,0 +1,210 @@
+"""GPU parity of the batched solve (los_batch_*) against the CPU oracle run on
+each model alone, through the C ABI.
+
+Each model of a batch is an independent solve on its own subset of the master
+k grid; the oracle solves it that way (FP64, S rounded to FP32 as the batch
+receives it).  Bounds as for the mixed-precision projection: per model and
+pair, |C - C_ref| <= max(1e-4 |C_ref|, 2.2 eps CA) on the small grids
+(CA = 4 pi sum w P A_a A_b, eps the normwise Delta bound of the precision),
+and 1e-4 relative (TE relative to sqrt(TT EE)) on the full-size batch.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_25110_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN_C4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_cl_oracle.txt")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_2509_25110_amd import los
+    c = los.Context()
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def small_batch(n=6, seed=7, lmax_range=(60, 160), nk_range=(30, 90), master_nk=120,
+                master_kmax=0.05, ntau=300):
+    draws = inputs.draw_models(n, seed=seed, lmax_range=lmax_range, nk_range=nk_range)
+    return inputs.batch_inputs(draws, ntau=ntau, master_nk=master_nk, master_kmax=master_kmax)
+
+
+def solve(torch, ctx, b, prec, S=None, plan=None):
+    if plan is None:
+        plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                    prec=prec)
+    col, ncols = plan.los_batch_columns()
+    if S is None:
+        S = dev(torch, inputs.batch_sources_host(b, col, ncols))
+    cl = plan.los_batch_solve(b.tau0, dev(torch, b.k_master), dev(torch, b.tau),
+                              dev(torch, b.w_tau), S, dev(torch, b.w_lnk), dev(torch, b.Pk))
+    torch.cuda.synchronize()
+    return plan, S, cl.cpu().numpy()
+
+
+def eps_for(prec, ntau):
+    e = (ntau + 2) * 2.0 ** -24
+    return e + 3 * 2.0 ** -16 if prec == 2 else e
+
+
+def oracle_model(b, m, col, S32):
+    """Oracle C_l (and the absolute-sum C_l) of model m solved alone, fed the same FP32 sources."""
+    lo, hi = int(b.koff[m]), int(b.koff[m + 1])
+    k = b.k_master[b.k_index[lo:hi]]
+    S = np.stack([S32[col[lo:hi] + s].astype(np.float64) for s in range(3)])
+    d, A = oracle.project(2, int(b.lmax[m]), k, b.tau, b.tau0, b.w_tau, S, with_abs=True)
+    return oracle.cl(d, b.w_lnk[lo:hi], b.Pk[lo:hi], b.pairs), \
+        oracle.cl(A, b.w_lnk[lo:hi], b.Pk[lo:hi], b.pairs)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_batch_small_vs_oracle(torch_dev, ctx, prec):
+    b = small_batch()
+    plan, S, cl = solve(torch_dev, ctx, b, prec)
+    col, _ = plan.los_batch_columns()
+    S32 = S.cpu().numpy()
+    info = plan.los_batch_info()
+    assert info["tuned"] == 1 and info["graph"] == 1
+    for m in range(b.nmodels):
+        L = int(b.lmax[m])
+        cref, CA = oracle_model(b, m, col, S32)
+        got = cl[m, :, :L - 1]
+        bound = np.maximum(1e-4 * np.abs(cref), 2.2 * eps_for(prec, b.ntau) * CA)
+        worst = float(np.max(np.abs(got - cref) / bound))
+        assert worst <= 1.0, (m, worst)
+        assert np.all(cl[m, :, L - 1:] == 0.0), m     # nothing beyond the model's l_max
+    plan.close()
+
+
+def test_batch_graph_replays_match_eager(torch_dev, ctx, monkeypatch):
+    """The captured graph, replayed several times with eager work and synchronisation in between,
+    gives the eager launch sequence's result bitwise every time."""
+    torch = torch_dev
+    b = small_batch(seed=11)
+    monkeypatch.setenv("LOS_BATCH_GRAPH", "0")
+    plan, S, eager = solve(torch, ctx, b, 2)
+    monkeypatch.delenv("LOS_BATCH_GRAPH")
+    args = (b.tau0, dev(torch, b.k_master), dev(torch, b.tau), dev(torch, b.w_tau), S,
+            dev(torch, b.w_lnk), dev(torch, b.Pk))
+    cl = torch.empty((b.nmodels, 4, int(b.lmax.max()) - 1), dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        cl.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.los_batch_solve(*args, cl=cl)
+        x = torch.randn(1000, device="cuda").sum()   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert np.isfinite(float(x))
+        np.testing.assert_array_equal(cl.cpu().numpy(), eager)
+    assert plan.los_batch_info()["graph"] == 1
+    plan.close()
+
+
+@pytest.mark.parametrize("mb,nc", [(1, 1), (4, 1), (2, 4), (4, 4)])
+def test_batch_tiles_agree(torch_dev, ctx, mb, nc, monkeypatch):
+    b = small_batch(seed=13)
+    monkeypatch.setenv("LOS_BATCH_TILE_MB", "2")
+    monkeypatch.setenv("LOS_BATCH_TILE_NC", "2")
+    plan, S, base = solve(torch_dev, ctx, b, 2)
+    plan.close()
+    monkeypatch.setenv("LOS_BATCH_TILE_MB", str(mb))
+    monkeypatch.setenv("LOS_BATCH_TILE_NC", str(nc))
+    plan, _, cl = solve(torch_dev, ctx, b, 2, S=S)
+    info = plan.los_batch_info()
+    assert (info["tile_mb"], info["tile_nc"]) == (mb, nc)
+    np.testing.assert_array_equal(cl, base)
+    plan.close()
+
+
+def test_batch_chunking(torch_dev, ctx, monkeypatch):
+    """A workspace of one Bessel table per chunk (many chunks) matches one chunk to rounding."""
+    b = small_batch(seed=17)
+    plan, S, base = solve(torch_dev, ctx, b, 1)
+    assert plan.los_batch_info()["chunks"] == 1
+    plan.close()
+    monkeypatch.setenv("LOS_JTAB_MIB", "1")
+    plan, _, cl = solve(torch_dev, ctx, b, 1, S=S)
+    assert plan.los_batch_info()["chunks"] > 10
+    scale = np.maximum(np.abs(base), 1e-300)
+    assert np.max(np.abs(cl - base) / scale) <= 1e-12
+    plan.close()
+
+
+def test_batch_one_model_matches_projection(torch_dev, ctx):
+    """A batch of one model equals los_project + cl_integrate on that model's grid (same FP32
+    sources, same precision) to FP64 rounding of the k sum."""
+    torch = torch_dev
+    b = small_batch(n=1, seed=19)
+    plan, S, cl = solve(torch, ctx, b, 2)
+    col, _ = plan.los_batch_columns()
+    S32 = S.cpu().numpy()
+    lo, hi = int(b.koff[0]), int(b.koff[1])
+    Sm = np.stack([S32[col[lo:hi] + s] for s in range(3)])
+    k = b.k_master[b.k_index[lo:hi]]
+    L = int(b.lmax[0])
+    d = ctx.los_project(2, L, dev(torch, k), dev(torch, b.tau), b.tau0, dev(torch, b.w_tau),
+                        dev(torch, Sm), prec=2)
+    c = ctx.cl_integrate(d, dev(torch, b.w_lnk[lo:hi]), dev(torch, b.Pk[lo:hi]), b.pairs)
+    ref = c.cpu().numpy()
+    assert np.max(np.abs(cl[0] - ref) / np.maximum(np.abs(ref), 1e-300)) <= 1e-12
+    plan.close()
+
+
+def test_batch_invalid_arguments(torch_dev, ctx):
+    from paper_2509_25110_amd import los
+    b = small_batch(n=2)
+    bad = b.k_index.copy()
+    bad[1] = bad[0]                      # not increasing
+    with pytest.raises(los.LosError):
+        ctx.los_batch_create(b.lmax, b.koff, bad, b.k_master.size, b.ntau, b.pairs)
+    with pytest.raises(los.LosError):
+        ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs, prec=0)
+
+
+def test_c4_full_size_sampled(torch_dev, ctx):
+    """The 256-model batch (l_max in [1500, 5000], 2000..8000 k of the 8000-point master grid,
+    3000 tau) in the configuration bench.py times: the C_l of the golden models within 1e-4 of
+    the FP64 oracle."""
+    torch = torch_dev
+    b = inputs.batch_inputs(inputs.draw_models(256))
+    plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                prec=2)
+    col, ncols = plan.los_batch_columns()
+    S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
+    inputs.batch_sources_device(b, col, S, torch)
+    _, _, cl = solve(torch, ctx, b, 2, S=S, plan=plan)
+    assert np.all(np.isfinite(cl))
+    gold = np.loadtxt(GOLDEN_C4)
+    worst = 0.0
+    for m in np.unique(gold[:, 0]).astype(int):
+        g = gold[gold[:, 0] == m]
+        ls = g[:, 1].astype(int) - 2
+        ref = g[:, 2:].T
+        got = cl[m][:, ls]
+        for p, (a, c) in enumerate(b.pairs):
+            if a == c:
+                rel = np.abs(got[p] / ref[p] - 1)
+            else:
+                rel = np.abs(got[p] - ref[p]) / np.sqrt(ref[b.pairs.index((a, a))] *
+                                                        ref[b.pairs.index((c, c))])
+            worst = max(worst, float(np.max(rel)))
+    print("C4 batch: max C_l rel err vs oracle %.3e (models %s)" % (worst, np.unique(gold[:, 0])))
+    assert worst <= 1e-4
+    plan.close()
