@@ -198,6 +198,71 @@ int los_batch_solve(los_batch *plan, double tau0, const double *k_master, const 
 
 void los_batch_destroy(los_batch *plan);
 
+/*
+ * C_l emulator.  The paper motivates fast repeated solves for parameter
+ * sampling (Sec. 1) but defines no emulator; this one is specified here.
+ * A network maps nparam source parameters p (scaled to u = 2 (p - lo) /
+ * (hi - lo) - 1) to whitened PCA coefficients of the 4 transformed spectra
+ * y = (log TT, log EE, asinh(TE / t_l), log PP) over nl multipoles:
+ * `depth` GELU layers of `width` units, then a linear layer of 4 * ncomp
+ * outputs, FP32 on the matrix cores.  `members` networks form an ensemble
+ * whose spread is the error estimate.  Parameters of one member (nparams
+ * floats): for each layer, W (out x in, row-major) then b (out).
+ *
+ * emu_create: 1 <= nparam <= 64, 1 <= nl <= 20000, 1 <= ncomp <= 104 and
+ *   ncomp <= nl, 1 <= width <= 4096, 1 <= depth <= 16, 1 <= members <= 16;
+ *   weights Glorot-uniform from SplitMix64(seed).
+ * emu_train (device params[n][nparam], cl[n][4][nl] with TT, EE, PP > 0;
+ *   host lo, hi [nparam]; host loss_hist[members * epochs] or NULL):
+ *   t_l = lower median of |TE_l| (from at most 8192 evenly strided rows);
+ *   per spectrum the mean and top ncomp covariance eigenvectors (FP64
+ *   randomised subspace iteration, Rayleigh-Ritz) and one coefficient scale
+ *   sigma_s = sqrt(variance of the kept components) (stored per component);
+ *   targets z = coefficients / sigma_s; then every member is re-initialised
+ *   and trained by emu_fit.  n >= ncomp + 8.
+ * emu_fit (device u[n][nparam], z[n][4 ncomp], float): Adam (0.9, 0.999,
+ *   1e-8) on the mean squared error, minibatches of `batch` rows from a
+ *   SplitMix64 Fisher-Yates shuffle per epoch (no shuffle when batch >= n),
+ *   step size lr (0.01 + 0.99 (1 + cos(pi (t-1) / T)) / 2) at step t of T;
+ *   moments reset at the start.  loss_hist[epochs] (host, or NULL): mean
+ *   minibatch loss per epoch.
+ * emu_infer (device params[n][nparam] -> cl[n][4][nl] double, err[n] float,
+ *   need_fallback[n] uint8): cl = member mean of the reconstructed spectra;
+ *   err = max over spectra, l and members of |C_e - C_mean| / scale (scale
+ *   |C_mean|, for TE sqrt(C_TT C_EE)); need_fallback = !(err <= threshold).
+ * emu_forward / emu_loss_grad (device, float): one member's network output
+ *   out[n][4 ncomp], and the loss (device, 1 float) with its gradient
+ *   (device, nparams floats).
+ * emu_get_params / emu_set_params (host, nparams floats of one member);
+ * emu_get_pca / emu_set_pca (host): lo, hi [nparam], mean [4][nl],
+ *   basis [4][nl][ncomp], sigma [4][ncomp], te_scale [nl].
+ * Calls are enqueued on `stream` except those with host outputs, which
+ * return when the values are copied.  Not thread-safe per emulator.
+ */
+typedef struct los_emu los_emu;
+
+int emu_create(los_ctx *ctx, int32_t nparam, int32_t nl, int32_t ncomp, int32_t width,
+               int32_t depth, int32_t members, uint64_t seed, los_emu **emu);
+void emu_destroy(los_emu *emu);
+int emu_nparams(const los_emu *emu, int64_t *count);
+int emu_get_params(const los_emu *emu, int32_t member, float *host);
+int emu_set_params(los_emu *emu, int32_t member, const float *host);
+int emu_get_pca(const los_emu *emu, double *lo, double *hi, double *mean, double *basis,
+                double *sigma, double *te_scale);
+int emu_set_pca(los_emu *emu, const double *lo, const double *hi, const double *mean,
+                const double *basis, const double *sigma, const double *te_scale);
+int emu_forward(los_emu *emu, int32_t member, const float *u, int64_t n, float *out,
+                void *stream);
+int emu_loss_grad(los_emu *emu, int32_t member, const float *u, const float *z, int64_t n,
+                  float *loss, float *grad, void *stream);
+int emu_fit(los_emu *emu, int32_t member, const float *u, const float *z, int64_t n,
+            int32_t epochs, int32_t batch, double lr, float *loss_hist, void *stream);
+int emu_train(los_emu *emu, const double *params, const double *lo, const double *hi,
+              const double *cl, int64_t n, int32_t epochs, int32_t batch, double lr,
+              float *loss_hist, void *stream);
+int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *err,
+              uint8_t *need_fallback, double threshold, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

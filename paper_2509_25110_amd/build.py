@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblos.so")
 
 SOURCES = ["los_api.cpp", "bessel_table.hip", "project_fp64.hip", "cl_reduce.hip", "jtable.hip",
-           "project_mfma.hip", "batch_cl.hip", "batch_api.cpp"]
+           "project_mfma.hip", "batch_cl.hip", "batch_api.cpp", "emu_kernels.hip", "emu_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -31,16 +31,28 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC]
 
 
-def _headers():
-    hs = [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
-    hs += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
-    return hs
+def _headers(src_path, seen=None):
+    """Project headers that `src_path` includes, directly or through other project headers."""
+    seen = set() if seen is None else seen
+    for line in open(src_path):
+        line = line.strip()
+        if not line.startswith('#include "'):
+            continue
+        name = line.split('"')[1]
+        for d in (CSRC, INCLUDE):
+            h = os.path.join(d, name)
+            if os.path.exists(h) and h not in seen:
+                seen.add(h)
+                _headers(h, seen)
+                break
+    return sorted(seen)
 
 
 def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if incremental and os.path.exists(obj):
-        newest = max(os.path.getmtime(p) for p in _headers() + [os.path.join(CSRC, src)])
+        path = os.path.join(CSRC, src)
+        newest = max(os.path.getmtime(p) for p in _headers(path) + [path])
         if os.path.getmtime(obj) > newest:
             return obj
     cmd = [HIPCC, *CFLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]

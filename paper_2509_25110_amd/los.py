@@ -34,7 +34,10 @@ _STATUS = {1: "LOS_ERR_INVALID", 2: "LOS_ERR_HIP", 3: "LOS_ERR_OOM", 4: "LOS_ERR
 # every symbol include/los.h declares
 EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
            "los_bessel_table", "los_project", "cl_integrate", "los_batch_create",
-           "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_destroy")
+           "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_destroy",
+           "emu_create", "emu_destroy", "emu_nparams", "emu_get_params", "emu_set_params",
+           "emu_get_pca", "emu_set_pca", "emu_forward", "emu_loss_grad", "emu_fit", "emu_train",
+           "emu_infer")
 
 
 class LosError(RuntimeError):
@@ -75,6 +78,26 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.los_batch_solve.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.los_batch_destroy.restype = None
     lib.los_batch_destroy.argtypes = [vp]
+    u64 = ctypes.c_uint64
+    sig = {
+        "emu_create": [vp, i32, i32, i32, i32, i32, i32, u64, ctypes.POINTER(vp)],
+        "emu_nparams": [vp, ctypes.POINTER(i64)],
+        "emu_get_params": [vp, i32, vp],
+        "emu_set_params": [vp, i32, vp],
+        "emu_get_pca": [vp, vp, vp, vp, vp, vp, vp],
+        "emu_set_pca": [vp, vp, vp, vp, vp, vp, vp],
+        "emu_forward": [vp, i32, vp, i64, vp, vp],
+        "emu_loss_grad": [vp, i32, vp, vp, i64, vp, vp, vp],
+        "emu_fit": [vp, i32, vp, vp, i64, i32, i32, dbl, vp, vp],
+        "emu_train": [vp, vp, vp, vp, vp, i64, i32, i32, dbl, vp, vp],
+        "emu_infer": [vp, vp, i64, vp, vp, vp, dbl, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = args
+    lib.emu_destroy.restype = None
+    lib.emu_destroy.argtypes = [vp]
     return lib
 
 
@@ -191,6 +214,117 @@ class Context:
                          nsrc: int = 3) -> "Batch":
         """Plan a batch (host arrays); see Batch."""
         return Batch(self, lmax, koff, k_index, nk_master, ntau, pairs, prec, nsrc)
+
+
+class Emulator:
+    """A los_emu (entry points emu_*): ensemble MLP emulator of the 4 spectra."""
+
+    def __init__(self, ctx: Context, nparam: int, nl: int, ncomp: int = 96, width: int = 512,
+                 depth: int = 4, members: int = 4, seed: int = 1):
+        h = ctypes.c_void_p()
+        _check(lib().emu_create(ctx.handle, nparam, nl, ncomp, width, depth, members, seed,
+                                ctypes.byref(h)))
+        self._h = h
+        self.nparam, self.nl, self.ncomp, self.members = nparam, nl, ncomp, members
+        self.nout = 4 * ncomp
+        n = ctypes.c_int64()
+        _check(lib().emu_nparams(h, ctypes.byref(n)))
+        self.nparams = int(n.value)
+
+    def emu_get_params(self, member: int):
+        import numpy as np
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().emu_get_params(self._h, member, out.ctypes.data))
+        return out
+
+    def emu_set_params(self, member: int, theta):
+        import numpy as np
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.size != self.nparams:
+            raise ValueError("expected %d parameters" % self.nparams)
+        _check(lib().emu_set_params(self._h, member, t.ctypes.data))
+
+    def emu_get_pca(self):
+        import numpy as np
+        lo = np.empty(self.nparam); hi = np.empty(self.nparam)
+        mean = np.empty((4, self.nl)); basis = np.empty((4, self.nl, self.ncomp))
+        sigma = np.empty((4, self.ncomp)); t = np.empty(self.nl)
+        _check(lib().emu_get_pca(self._h, lo.ctypes.data, hi.ctypes.data, mean.ctypes.data,
+                                 basis.ctypes.data, sigma.ctypes.data, t.ctypes.data))
+        return dict(lo=lo, hi=hi, mean=mean, basis=basis, sigma=sigma, te_scale=t)
+
+    def emu_set_pca(self, lo, hi, mean, basis, sigma, te_scale):
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (lo, hi, mean, basis, sigma,
+                                                                    te_scale)]
+        _check(lib().emu_set_pca(self._h, *[a.ctypes.data for a in arrs]))
+
+    def emu_forward(self, member: int, u: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+        n = u.shape[0]
+        _need(u, torch.float32, n * self.nparam, "u")
+        if out is None:
+            out = torch.empty((n, self.nout), dtype=torch.float32, device=u.device)
+        _check(lib().emu_forward(self._h, member, _ptr(u), n, _ptr(out), _stream(stream)))
+        return out
+
+    def emu_loss_grad(self, member: int, u: torch.Tensor, z: torch.Tensor, stream=None):
+        n = u.shape[0]
+        _need(u, torch.float32, n * self.nparam, "u")
+        _need(z, torch.float32, n * self.nout, "z")
+        loss = torch.empty(1, dtype=torch.float32, device=u.device)
+        grad = torch.empty(self.nparams, dtype=torch.float32, device=u.device)
+        _check(lib().emu_loss_grad(self._h, member, _ptr(u), _ptr(z), n, _ptr(loss), _ptr(grad),
+                                   _stream(stream)))
+        return loss, grad
+
+    def emu_fit(self, member: int, u: torch.Tensor, z: torch.Tensor, epochs: int, batch: int,
+                lr: float, stream=None):
+        import numpy as np
+        n = u.shape[0]
+        _need(u, torch.float32, n * self.nparam, "u")
+        _need(z, torch.float32, n * self.nout, "z")
+        hist = np.zeros(epochs, dtype=np.float32)
+        _check(lib().emu_fit(self._h, member, _ptr(u), _ptr(z), n, epochs, batch, float(lr),
+                             hist.ctypes.data, _stream(stream)))
+        return hist
+
+    def emu_train(self, params: torch.Tensor, lo, hi, cl: torch.Tensor, epochs: int = 200,
+                  batch: int = 256, lr: float = 1e-3, stream=None):
+        import numpy as np
+        n = params.shape[0]
+        _need(params, torch.float64, n * self.nparam, "params")
+        _need(cl, torch.float64, n * 4 * self.nl, "cl")
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        hist = np.zeros(self.members * epochs, dtype=np.float32)
+        _check(lib().emu_train(self._h, _ptr(params), lo.ctypes.data, hi.ctypes.data, _ptr(cl), n,
+                               epochs, batch, float(lr), hist.ctypes.data, _stream(stream)))
+        return hist.reshape(self.members, epochs)
+
+    def emu_infer(self, params: torch.Tensor, threshold: float = 1e-3, cl=None, stream=None):
+        n = params.shape[0]
+        _need(params, torch.float64, n * self.nparam, "params")
+        if cl is None:
+            cl = torch.empty((n, 4, self.nl), dtype=torch.float64, device=params.device)
+        err = torch.empty(n, dtype=torch.float32, device=params.device)
+        flag = torch.empty(n, dtype=torch.uint8, device=params.device)
+        _check(lib().emu_infer(self._h, _ptr(params), n, _ptr(cl), _ptr(err), _ptr(flag),
+                               float(threshold), _stream(stream)))
+        return cl, err, flag
+
+    def emu_destroy(self):
+        if self._h is not None and self._h.value:
+            lib().emu_destroy(self._h)
+        self._h = None
+
+    close = emu_destroy
+
+    def __del__(self):
+        try:
+            self.emu_destroy()
+        except Exception:
+            pass
 
 
 class Batch:

@@ -1,0 +1,258 @@
+"""GPU parity of the C_l emulator (emu_*) against the FP64 CPU oracle
+(oracle/emu_oracle.py), through the C ABI, plus an end-to-end run on spectra
+from the batched solver.
+
+Weights and PCA tables given to both sides are made on the host (numpy, seeded,
+or the oracle's own PCA); nothing the GPU computes is fed to the oracle.
+Bounds (FP32 arithmetic with FP32 accumulation over K terms against FP64):
+network outputs and gradients normwise 2e-5 of their largest entry; Adam
+updates of well-determined parameters within 1e-3 lr per step; PCA basis
+within a factor 1 + 1e-6 of the exact truncation floor; reconstructed C_l
+2e-4 relative.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import emu_oracle as eo
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_2509_25110_amd import los
+    c = los.Context()
+    yield c
+    c.close()
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t.to(dtype) if dtype is not None else t).cuda()
+
+
+def glorot(rng, sizes):
+    parts = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / (a + b))
+        parts.append(rng.uniform(-lim, lim, size=a * b))
+        parts.append(rng.normal(size=b) * 0.1)
+    return np.concatenate(parts).astype(np.float32)
+
+
+def make_emu(ctx, nparam=5, nl=40, ncomp=8, width=64, depth=3, members=2, seed=1):
+    from paper_2509_25110_amd import los
+    return los.Emulator(ctx, nparam, nl, ncomp=ncomp, width=width, depth=depth, members=members,
+                        seed=seed)
+
+
+def test_emu_forward_and_gradient_vs_oracle(torch_dev, ctx):
+    torch = torch_dev
+    emu = make_emu(ctx)
+    sizes = eo.layer_sizes(5, 64, 3, emu.nout)
+    assert emu.nparams == eo.n_params(sizes)
+    rng = np.random.default_rng(21)
+    theta = glorot(rng, sizes)
+    emu.emu_set_params(1, theta)
+    u = rng.uniform(-1, 1, size=(37, 5)).astype(np.float32)
+    z = rng.normal(size=(37, emu.nout)).astype(np.float32)
+    out = emu.emu_forward(1, dev(torch, u)).cpu().numpy()
+    ref, _, _ = eo.forward(theta.astype(np.float64), sizes, u.astype(np.float64))
+    assert np.max(np.abs(out - ref)) <= 2e-5 * np.max(np.abs(ref))
+    loss, grad = emu.emu_loss_grad(1, dev(torch, u), dev(torch, z))
+    lref, gref = eo.loss_and_grad(theta.astype(np.float64), sizes, u.astype(np.float64),
+                                  z.astype(np.float64))
+    assert abs(float(loss.item()) - lref) <= 2e-5 * lref
+    g = grad.cpu().numpy()
+    assert np.max(np.abs(g - gref)) <= 2e-5 * np.max(np.abs(gref))
+    np.testing.assert_array_equal(emu.emu_get_params(1), theta)   # set/get round trip
+    emu.close()
+
+
+def test_emu_fit_full_batch_matches_oracle_adam(torch_dev, ctx):
+    """Three full-batch Adam steps (no shuffle) from the same weights: the parameters whose
+    gradient is well above FP32 noise move as the oracle's do."""
+    torch = torch_dev
+    emu = make_emu(ctx, width=32, depth=2, members=1)
+    sizes = eo.layer_sizes(5, 32, 2, emu.nout)
+    rng = np.random.default_rng(22)
+    theta = glorot(rng, sizes)
+    emu.emu_set_params(0, theta)
+    u = rng.uniform(-1, 1, size=(50, 5)).astype(np.float32)
+    z = rng.normal(size=(50, emu.nout)).astype(np.float32)
+    lr, steps = 1e-2, 3
+    hist = emu.emu_fit(0, dev(torch, u), dev(torch, z), epochs=steps, batch=50, lr=lr)
+    got = emu.emu_get_params(0).astype(np.float64)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    losses, g1 = [], None
+    for t in range(1, steps + 1):
+        loss, g = eo.loss_and_grad(th, sizes, u.astype(np.float64), z.astype(np.float64))
+        losses.append(loss)
+        g1 = g if g1 is None else g1
+        sched = 0.01 + 0.99 * 0.5 * (1 + np.cos(np.pi * (t - 1) / steps))
+        th, m, v = eo.adam_step(th, g, m, v, t, lr * sched)
+    np.testing.assert_allclose(hist, losses, rtol=1e-4)
+    ok = np.abs(g1) > 1e-3 * np.max(np.abs(g1))
+    assert ok.sum() > 0.5 * ok.size
+    assert np.max(np.abs(got - th)[ok]) <= 1e-3 * lr * steps
+    emu.close()
+
+
+def synthetic_spectra(rng, n, nl, rank=30):
+    """Smooth positive TT/EE/PP and signed TE with a decaying PCA spectrum (factor 0.6 per
+    component) driven by 5 parameters."""
+    p = rng.uniform(-1, 1, size=(n, 5))
+    ell = np.linspace(0, 1, nl)
+    phis = np.stack([np.cos(np.pi * (i + 1) * ell) for i in range(rank)])   # [rank, nl]
+    cl = np.empty((n, 4, nl))
+    for s in range(4):
+        W = rng.normal(size=(5, rank))
+        a = np.tanh(p @ W + 0.3 * np.sin(3 * p @ W)) * (0.6 ** np.arange(rank))
+        y = -3.0 - 2.0 * ell + 0.5 * s + a @ phis
+        cl[:, s] = np.exp(y)
+    cl[:, 2] = np.sin(7 * ell + 0.3)[None, :] * cl[:, 2]    # TE changes sign
+    return p, cl
+
+
+def test_emu_pca_vs_oracle_floor(torch_dev, ctx):
+    torch = torch_dev
+    rng = np.random.default_rng(23)
+    n, nl, ncomp = 400, 120, 12
+    p, cl = synthetic_spectra(rng, n, nl)
+    emu = make_emu(ctx, nl=nl, ncomp=ncomp, width=16, depth=1, members=1)
+    lo, hi = -np.ones(5), np.ones(5)
+    emu.emu_train(dev(torch, p), lo, hi, dev(torch, cl), epochs=1, batch=64, lr=1e-3)
+    torch.cuda.synchronize()
+    pca = emu.emu_get_pca()
+    t = eo.te_scale(cl[:, 2])
+    np.testing.assert_array_equal(pca["te_scale"], t)            # exact selection
+    y = eo.transform(cl, t)
+    mu, V, w = eo.pca_fit(y, ncomp)
+    floor = eo.pca_floor(w, ncomp)
+    np.testing.assert_allclose(pca["mean"], mu, rtol=1e-12, atol=1e-12)
+    for s in range(4):
+        X = y[:, s] - mu[s]
+        B = pca["basis"][s]
+        np.testing.assert_allclose(B.T @ B, np.eye(ncomp), atol=1e-10)
+        rec = X @ B @ B.T
+        mse = np.mean(np.sum((X - rec) ** 2, axis=1))
+        assert floor[s] * (1 - 1e-9) <= mse <= floor[s] * (1 + 1e-6) + 1e-14, (s, mse, floor[s])
+        np.testing.assert_allclose(pca["sigma"][s], eo.target_scale(w, ncomp)[s], rtol=1e-9)
+    emu.close()
+
+
+def test_emu_infer_vs_oracle(torch_dev, ctx):
+    """Given the oracle's PCA tables and host-made weights, the ensemble reconstruction, mean and
+    error estimate agree with the oracle's."""
+    torch = torch_dev
+    rng = np.random.default_rng(24)
+    n, nl, ncomp, members = 300, 80, 8, 3
+    p, cl = synthetic_spectra(rng, n, nl)
+    t = eo.te_scale(cl[:, 2])
+    y = eo.transform(cl, t)
+    mu, V, w = eo.pca_fit(y, ncomp)
+    sigma = np.repeat(eo.target_scale(w, ncomp)[:, None], ncomp, axis=1)
+    lo, hi = -np.ones(5), np.ones(5)
+    emu = make_emu(ctx, nl=nl, ncomp=ncomp, width=32, depth=2, members=members)
+    emu.emu_set_pca(lo, hi, mu, V, sigma, t)
+    sizes = eo.layer_sizes(5, 32, 2, 4 * ncomp)
+    thetas = [glorot(rng, sizes) * 0.3 for _ in range(members)]
+    for e, th in enumerate(thetas):
+        emu.emu_set_params(e, th)
+    q = rng.uniform(-1, 1, size=(57, 5))
+    c, err, flag = emu.emu_infer(dev(torch, q), threshold=0.05)
+    c, err, flag = c.cpu().numpy(), err.cpu().numpy(), flag.cpu().numpy()
+    u = 2 * (q - lo) / (hi - lo) - 1
+    cls = []
+    for th in thetas:
+        out, _, _ = eo.forward(th.astype(np.float64), sizes, u)
+        ys = np.empty((57, 4, nl))
+        for s in range(4):
+            ys[:, s] = mu[s] + (out[:, s * ncomp:(s + 1) * ncomp] * sigma[s]) @ V[s].T
+        cls.append(eo.inverse_transform(ys, t))
+    mref, eref = eo.ensemble_stats(np.stack(cls))
+    scale = np.abs(mref).copy()
+    scale[:, 2] = np.sqrt(mref[:, 0] * mref[:, 1])
+    assert np.max(np.abs(c - mref) / scale) <= 2e-4
+    np.testing.assert_allclose(err, eref, rtol=1e-2, atol=2e-4)
+    clear = np.abs(eref - 0.05) > 1e-3
+    np.testing.assert_array_equal(flag[clear], (eref > 0.05)[clear])
+    emu.close()
+
+
+def test_emu_trained_on_batch_solver_beats_solve(torch_dev, ctx):
+    """End to end: spectra from the batched solver (small grids: l <= 200, 120 k, 400 tau) train
+    the emulator (1024 draws of the batch prior); on 128 held-out draws the plain solve judges
+    it.  The ensemble error estimate must track the true error, every model whose true error is
+    above the fallback threshold must mostly be flagged (an ensemble spread is an estimate, not a
+    bound: at least 80% of them), and per spectrum the emulator must cost less than the solve it
+    replaces."""
+    torch = torch_dev
+    from paper_2509_25110_amd import inputs
+
+    def solve_set(n, seed):
+        draws = inputs.draw_models(n, seed=seed, lmax_range=(200, 200), nk_range=(120, 120))
+        b = inputs.batch_inputs(draws, ntau=400, master_nk=120, master_kmax=0.06)
+        plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                    prec=2)
+        col, ncols = plan.los_batch_columns()
+        S = dev(torch, inputs.batch_sources_host(b, col, ncols))
+        args = (b.tau0, dev(torch, b.k_master), dev(torch, b.tau), dev(torch, b.w_tau), S,
+                dev(torch, b.w_lnk), dev(torch, b.Pk))
+        cl = plan.los_batch_solve(*args)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cl = plan.los_batch_solve(*args)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        params = np.array([[d.tau_star, d.width, d.a_isw, d.n_s, d.ln1e10As] for d in draws])
+        plan.close()
+        return params, cl, dt
+
+    lo = np.array([260.0, 15.0, 0.0, 0.92, 2.9])
+    hi = np.array([300.0, 25.0, 0.2, 1.0, 3.2])
+    ptr, ctr, _ = solve_set(1024, 1)
+    pte, cte, solve_s = solve_set(128, 2)
+    nl = ctr.shape[2]
+    emu = make_emu(ctx, nl=nl, ncomp=24, width=128, depth=3, members=4, seed=5)
+    hist = emu.emu_train(dev(torch, ptr), lo, hi, ctr, epochs=300, batch=128, lr=2e-3)
+    assert np.all(hist[:, -1] < 0.01 * hist[:, 0]), hist[:, [0, -1]]
+    thr = 2e-2
+    c, err, flag = emu.emu_infer(dev(torch, pte), threshold=thr)
+    c, err, flag = c.cpu().numpy(), err.cpu().numpy(), flag.cpu().numpy()
+    ref = cte.cpu().numpy()
+    scale = np.abs(ref).copy()
+    scale[:, 2] = np.sqrt(ref[:, 0] * ref[:, 1])
+    true_err = np.max(np.abs(c - ref) / scale, axis=(1, 2))
+    ratio = float(np.median(err / true_err))
+    big = np.repeat(pte, 32, axis=0)                 # 4096 parameter sets
+    P = dev(torch, big)
+    emu.emu_infer(P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    emu.emu_infer(P)
+    torch.cuda.synchronize()
+    emu_s = (time.perf_counter() - t0) / big.shape[0]
+    solve_per = solve_s / pte.shape[0]
+    print("emulator held-out: median err %.2e, max %.2e, flagged %d/%d, est/true median %.2f; "
+          "%.2f us per spectrum vs solve %.2f us"
+          % (np.median(true_err), true_err.max(), int(flag.sum()), flag.size, ratio,
+             emu_s * 1e6, solve_per * 1e6))
+    assert np.median(true_err) < 5e-2
+    assert 1 / 3 < ratio < 3
+    bad = true_err > 3 * thr
+    assert np.mean(flag[bad]) >= 0.8, (int(flag[bad].sum()), int(bad.sum()))
+    assert emu_s < solve_per
+    emu.close()
