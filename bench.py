@@ -260,6 +260,131 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+EMU_LO = np.array([260.0, 15.0, 0.0, 0.92, 2.9])     # tau*, width, ISW amp, n_s, ln(1e10 A_s)
+EMU_HI = np.array([300.0, 25.0, 0.2, 1.0, 3.2])
+
+
+def solve_models(ctx, draws, prec, torch, chunk=256):
+    """Batched solve of drawn models (all on the full master grid, l_max 5000) in plans of
+    `chunk` models; returns (params [n, 5], cl [n, 4, 4999] on the device, solve seconds)."""
+    from paper_2509_25110_amd import inputs
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    out, secs = [], 0.0
+    for c0 in range(0, len(draws), chunk):
+        b = inputs.batch_inputs(draws[c0:c0 + chunk])
+        plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                    prec=prec)
+        col, ncols = plan.los_batch_columns()
+        S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
+        inputs.batch_sources_device(b, col, S, torch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cl = plan.los_batch_solve(b.tau0, dv(b.k_master), dv(b.tau), dv(b.w_tau), S, dv(b.w_lnk),
+                                  dv(b.Pk))
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        out.append(cl)
+        del S
+        plan.close()
+        print("solved %d / %d models" % (min(c0 + chunk, len(draws)), len(draws)),
+              file=sys.stderr, flush=True)
+    params = np.array([[d.tau_star, d.width, d.a_isw, d.n_s, d.ln1e10As] for d in draws])
+    return params, torch.cat(out), secs
+
+
+def run_emulator(args):
+    """C5: emulator trained on batch-solver spectra (l = 2..5000, 8000 master k, 3000 tau),
+    inference on batches of 4096, held-out error judged by the plain solve, fallback above
+    the error-estimate threshold."""
+    import torch
+    from paper_2509_25110_amd import inputs, los
+    torch.cuda.set_device(0)
+    ctx = los.Context()
+    pin = dict(lmax_range=(5000, 5000), nk_range=(8000, 8000))
+    tr = inputs.draw_models(args.emu_train, seed=1, **pin)
+    te = inputs.draw_models(256, seed=2, **pin)
+    ptr, ctr, gen_s = solve_models(ctx, tr, 2, torch)
+    pte, cte, solve_s = solve_models(ctx, te, 2, torch)
+    nl = ctr.shape[2]
+    emu = los.Emulator(ctx, 5, nl, ncomp=96, width=512, depth=4, members=4, seed=7)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = emu.emu_train(dv(ptr), EMU_LO, EMU_HI, ctr, epochs=args.emu_epochs, batch=256,
+                         lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    thr = 1e-3
+    c, err, flag = emu.emu_infer(dv(pte), threshold=thr)
+    c, err, flag = c.cpu().numpy(), err.cpu().numpy(), flag.cpu().numpy()
+    ref = cte.cpu().numpy()
+    scale = np.abs(ref).copy()
+    scale[:, 2] = np.sqrt(ref[:, 0] * ref[:, 1])
+    true_err = np.max(np.abs(c - ref) / scale, axis=(1, 2))
+    # inference throughput at batch 4096 (held-out parameters repeated)
+    P = dv(np.repeat(pte, 16, axis=0))
+    cl_buf = torch.empty((P.shape[0], 4, nl), dtype=torch.float64, device="cuda")
+    emu.emu_infer(P, cl=cl_buf)
+    torch.cuda.synchronize()
+    K = args.steps
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(K):
+        emu.emu_infer(P, cl=cl_buf)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / K
+    emu_rate = P.shape[0] / (ms * 1e-3)
+    solve_rate = len(te) / solve_s
+    frac = float(np.mean(flag))
+    effective = 1.0 / (1.0 / emu_rate + frac / solve_rate)
+    # FP64 plain path on two held-out models
+    t64 = 0.0
+    for d in te[:2]:
+        w = inputs.model_workload(d)
+        a64 = (dv(w.k), dv(w.tau), w.tau0, dv(w.w_tau), dv(w.S))
+        ctx.los_project(w.lmin, w.lmax, *a64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dd = ctx.los_project(w.lmin, w.lmax, *a64)
+        ctx.cl_integrate(dd, dv(w.w_lnk), dv(w.Pk), w.pairs)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t1
+        del dd
+    flops = 4096 * 2.0 * (emu.nparams + 4 * 96 * nl) * emu.members
+    peak = PEAK["fp32_mfma"]
+    out = {
+        "metric": METRIC,
+        "value": emu_rate, "unit": "spectra/s", "n_gpus": 1, "steps": K, "warmup": 1,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 MLP and reconstruction, f64 C_l", "data": "synthetic",
+        "config": {"workload": "C5: emulator of TT/EE/TE/PP over l=2..5000, %d training spectra "
+                               "from the bf16x3 batched solver (8000 master k, 3000 tau), "
+                               "4 x MLP 5-512x4-384 GELU, PCA 96 per spectrum, inference "
+                               "batch 4096" % len(tr),
+                   "train_spectra": len(tr), "heldout_spectra": len(te), "epochs": args.emu_epochs,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak,
+                     "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / peak,
+                     "traffic": None, "kernel": "emu_infer (4 members: MLP + reconstruction)",
+                     "kernel_ms": ms,
+                     "work": "4096 x 4 members x 2 x (MLP params + 4 x 96 x %d)" % nl},
+        "heldout_err_median": float(np.median(true_err)),
+        "heldout_err_p90": float(np.quantile(true_err, 0.9)),
+        "heldout_err_max": float(true_err.max()),
+        "estimate_over_true_median": float(np.median(err / true_err)),
+        "fallback_threshold": thr, "fallback_fraction": frac,
+        "effective_spectra_per_s_with_fallback": effective,
+        "batch_solver_spectra_per_s": solve_rate,
+        "fp64_plain_path_spectra_per_s": 2.0 / t64,
+        "training_data_solve_s": gen_s, "train_s": train_s,
+        "final_loss": [float(x) for x in hist[:, -1]],
+    }
+    emu.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +395,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle sample: every n-th k row (default 4 for C2, 16 for C3)")
+    ap.add_argument("--emu-train", type=int, default=4096, help="C5: training spectra")
+    ap.add_argument("--emu-epochs", type=int, default=300, help="C5: training epochs")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="C4: also time the FP64 plain path on a sample of the batch's models")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -292,6 +419,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.config == "C4":
         return run_batch(args)
+    if args.config == "C5":
+        return run_emulator(args)
 
     import torch
     from paper_2509_25110_amd import inputs, los
