@@ -79,7 +79,7 @@ def cpu_baseline(wl, stride):
     per_spectrum = dt * wl.nk / rows.size
     return {"value": 1.0 / per_spectrum, "unit": "spectra/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%d of %d k rows (every %dth), all l and tau, %.1f s; scaled by nk/rows"
+            "sample": "%d of %d k rows (stride %d), all l and tau, %.1f s; scaled by nk/rows"
                       % (rows.size, wl.nk, stride, dt)}
 
 
@@ -394,7 +394,7 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=list(PRECS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
-                    help="oracle sample: every n-th k row (default 4 for C2, 16 for C3)")
+                    help="oracle sample: every n-th k row (default 1 for C2, 4 for C3)")
     ap.add_argument("--emu-train", type=int, default=4096, help="C5: training spectra")
     ap.add_argument("--emu-epochs", type=int, default=300, help="C5: training epochs")
     ap.add_argument("--fp64-compare", action="store_true",
@@ -507,7 +507,7 @@ def main():
         "max_rel_err_vs_oracle": err,
     }
     if not args.no_cpu_baseline and rank == 0:
-        stride = args.cpu_stride or {"C3": 16}.get(wl.name, 4)
+        stride = args.cpu_stride or {"C3": 4}.get(wl.name, 1)
         out["cpu_baseline"] = cpu_baseline(wl, stride)
     ctx.close()
     if rank == 0:

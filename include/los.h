@@ -176,8 +176,9 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
  *   cl[nmodels * npairs * (L - 1)] (double, written), L = max lmax:
  *     cl[(m * npairs + p) * (L - 1) + l - 2] = 4 pi sum_j w P Delta^a Delta^b,
  *     zero for l > lmax[m].
- * The first call times every compiled tile shape on the first chunk and keeps
- * the fastest; each new set of argument pointers is captured once into a HIP
+ * The first call times every compiled tile shape (including an LDS-staged
+ * 256 x 128 split-BF16x3 kernel) on two representative chunks and keeps the
+ * fastest; each new set of argument pointers is captured once into a HIP
  * graph that later calls replay.  A plan is not thread-safe.
  * los_batch_info (host): info[8] = {tile l blocks, tile column blocks, rows
  * per chunk, chunks, used master rows, max lmax, tuned, graph captured}.

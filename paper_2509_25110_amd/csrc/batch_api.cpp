@@ -10,9 +10,9 @@
 // its first column.  Rows are processed in chunks that fit a bounded device
 // workspace: Bessel tables (jtable.hip) -> MFMA product with transposed
 // output (project_mfma.hip) -> per-model C_l accumulation (batch_cl.hip).
-// The first solve times every compiled tile shape on the first chunk and
-// keeps the fastest (autotuner); the whole launch sequence is then captured
-// once into a HIP graph per set of argument pointers and replayed.
+// The first solve times every compiled tile shape on two representative
+// chunks and keeps the fastest (autotuner); the whole launch sequence is then
+// captured once into a HIP graph per set of argument pointers and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -171,13 +171,16 @@ int enqueue(los_batch *b, const SolveArgs &s, hipStream_t st) {
   return LOS_OK;
 }
 
-// Time every compiled tile shape on the first chunk (its Bessel table built
-// once); keep the fastest.  LOS_BATCH_TILE_MB / _NC pin a shape instead.
+// Time every compiled tile shape on two representative chunks (the middle
+// one and the last full one, where k and the Bessel band are largest), each
+// after building its Bessel table once; keep the fastest total.
+// LOS_BATCH_TILE_MB / _NC pin a shape instead; LOS_BATCH_TUNE=0 keeps {2, 4}.
 int autotune(los_batch *b, const SolveArgs &s, hipStream_t st) {
   const int mb = env_i("LOS_BATCH_TILE_MB", 0), nc = env_i("LOS_BATCH_TILE_NC", 0);
   if (mb > 0 && nc > 0) {
     los::GemmTile t{mb, nc};
-    if (!los::gemm_tile_supported(t))
+    if (!los::gemm_tile_supported(t) ||
+        (t.mb == los::kGemmTileLds.mb && t.nc == los::kGemmTileLds.nc && b->prec != LOS_BF16X3))
       return fail(LOS_ERR_INVALID, "los_batch_solve: tile %d x %d is not compiled", mb, nc);
     b->tile = t;
     b->tuned = true;
@@ -187,39 +190,59 @@ int autotune(los_batch *b, const SolveArgs &s, hipStream_t st) {
     b->tuned = true;
     return LOS_OK;
   }
-  const int cnt = (int)(b->chunk_row0[1] - b->chunk_row0[0]);
-  hipError_t e = los::jtable_launch(jargs(b, s, b->chunk_row0[0]), cnt, st);
-  if (e != hipSuccess) return hip_fail(e, "autotune: Bessel table launch");
+  int probe[2] = {b->nchunks / 2, b->nchunks - 1};
+  if (b->nchunks > 1 && b->chunk_row0[b->nchunks] - b->chunk_row0[b->nchunks - 1] < b->kc)
+    probe[1] = b->nchunks - 2;  // the last chunk is a short remainder
+  const int nprobe = probe[0] == probe[1] ? 1 : 2;
   hipEvent_t t0, t1;
+  hipError_t e;
   if ((e = hipEventCreate(&t0)) != hipSuccess) return hip_fail(e, "autotune: event");
   if ((e = hipEventCreate(&t1)) != hipSuccess) {
     (void)hipEventDestroy(t0);
     return hip_fail(e, "autotune: event");
   }
-  float best = 1e30f;
+  float total[los::kGemmTileCount] = {};
   int rc = LOS_OK;
-  for (int i = 0; i < los::kGemmTileCount && rc == LOS_OK; ++i) {
-    const los::GemmTile t = los::gemm_tile_at(i);
-    float ms = 0.f;
-    for (int rep = 0; rep < 2 && rc == LOS_OK; ++rep) {  // first run warms up
-      e = hipEventRecord(t0, st);
-      if (e == hipSuccess) e = los::mfma_gemm_launch(gargs(b, s, 0), b->prec, t, cnt,
-                                                      b->chunk_maxcol[0], st);
-      if (e == hipSuccess) e = hipEventRecord(t1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(t1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-      if (e != hipSuccess) rc = hip_fail(e, "autotune");
+  for (int pi = 0; pi < nprobe && rc == LOS_OK; ++pi) {
+    const int c = probe[pi];
+    const int cnt = (int)(b->chunk_row0[c + 1] - b->chunk_row0[c]);
+    e = los::jtable_launch(jargs(b, s, b->chunk_row0[c]), cnt, st);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "autotune: Bessel table launch");
+      break;
     }
-    b->tune_ms[i] = ms;
-    if (rc == LOS_OK && ms < best) {
-      best = ms;
-      b->tile = t;
+    for (int i = 0; i < los::kGemmTileCount && rc == LOS_OK; ++i) {
+      const los::GemmTile t = los::gemm_tile_at(i);
+      if (t.mb == los::kGemmTileLds.mb && t.nc == los::kGemmTileLds.nc && b->prec != LOS_BF16X3) {
+        total[i] = -1.f;  // not available in this precision
+        continue;
+      }
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && rc == LOS_OK; ++rep) {  // first run warms up
+        e = hipEventRecord(t0, st);
+        if (e == hipSuccess)
+          e = los::mfma_gemm_launch(gargs(b, s, c), b->prec, t, cnt, b->chunk_maxcol[c], st);
+        if (e == hipSuccess) e = hipEventRecord(t1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e != hipSuccess) rc = hip_fail(e, "autotune");
+      }
+      total[i] += ms;
     }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  if (rc == LOS_OK) b->tuned = true;
-  return rc;
+  if (rc != LOS_OK) return rc;
+  float best = 1e30f;
+  for (int i = 0; i < los::kGemmTileCount; ++i) {
+    b->tune_ms[i] = total[i];
+    if (total[i] >= 0.f && total[i] < best) {
+      best = total[i];
+      b->tile = los::gemm_tile_at(i);
+    }
+  }
+  b->tuned = true;
+  return LOS_OK;
 }
 
 }  // namespace

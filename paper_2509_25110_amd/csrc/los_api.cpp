@@ -106,7 +106,7 @@ int64_t jtab_chunk(int64_t nk, size_t per_k) {
 
 los::GemmTile gemm_tile_for(int max_ncol) {
   los::GemmTile t{env_int("LOS_GEMM_MB"), env_int("LOS_GEMM_NC")};
-  if (t.mb > 0 && t.nc > 0 && los::gemm_tile_supported(t)) return t;
+  if (t.mb > 0 && t.nc > 0 && los::gemm_tile_supported(t)) return t;  // (checked per precision at launch)
   if (max_ncol <= 16) return {4, 1};
   if (max_ncol <= 32) return {2, 2};
   return {2, 4};

@@ -78,9 +78,13 @@ struct GemmTile {
   int nc;  // 16-column blocks per wave
 };
 bool gemm_tile_supported(const GemmTile &t);
-// Tile shapes the batch autotuner tries.
-constexpr int kGemmTileCount = 7;
+// Tile shapes the batch autotuner tries.  The last, {16, 8} (256 rows x 128
+// columns per workgroup), is the LDS-staged kernel (project_mfma_lds.hip),
+// split-BF16x3 only.
+constexpr int kGemmTileCount = 8;
+constexpr GemmTile kGemmTileLds{16, 8};
 GemmTile gemm_tile_at(int i);
+hipError_t mfma_gemm_lds_launch(const GemmArgs &a, int kcount, int max_ncol, hipStream_t s);
 hipError_t mfma_gemm_launch(const GemmArgs &a, int prec, const GemmTile &t, int kcount,
                             int max_ncol, hipStream_t s);
 

@@ -178,11 +178,12 @@ hipError_t launch_p(const GemmArgs &a, const GemmTile &t, int kcount, int max_nc
 
 GemmTile gemm_tile_at(int i) {
   static const GemmTile tiles[kGemmTileCount] = {{1, 1}, {2, 1}, {4, 1}, {2, 2},
-                                                 {2, 4}, {4, 2}, {4, 4}};
+                                                 {2, 4}, {4, 2}, {4, 4}, kGemmTileLds};
   return tiles[i];
 }
 
 bool gemm_tile_supported(const GemmTile &t) {
+  if (t.mb == kGemmTileLds.mb && t.nc == kGemmTileLds.nc) return true;
   switch (t.mb * 16 + t.nc) {
     case 1 * 16 + 1: case 2 * 16 + 1: case 4 * 16 + 1: case 2 * 16 + 2:
     case 2 * 16 + 4: case 4 * 16 + 2: case 4 * 16 + 4:
@@ -194,6 +195,10 @@ bool gemm_tile_supported(const GemmTile &t) {
 
 hipError_t mfma_gemm_launch(const GemmArgs &a, int prec, const GemmTile &t, int kcount,
                             int max_ncol, hipStream_t s) {
+  if (t.mb == kGemmTileLds.mb && t.nc == kGemmTileLds.nc) {
+    if (prec != 2) return hipErrorInvalidValue;  // the staged kernel is split-BF16x3 only
+    return mfma_gemm_lds_launch(a, kcount, max_ncol, s);
+  }
   if (prec == 1) return launch_p<1>(a, t, kcount, max_ncol, s);
   return launch_p<2>(a, t, kcount, max_ncol, s);
 }

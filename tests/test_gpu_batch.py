@@ -117,7 +117,7 @@ def test_batch_graph_replays_match_eager(torch_dev, ctx, monkeypatch):
     plan.close()
 
 
-@pytest.mark.parametrize("mb,nc", [(1, 1), (4, 1), (2, 4), (4, 4)])
+@pytest.mark.parametrize("mb,nc", [(1, 1), (4, 1), (2, 4), (4, 4), (16, 8)])
 def test_batch_tiles_agree(torch_dev, ctx, mb, nc, monkeypatch):
     b = small_batch(seed=13)
     monkeypatch.setenv("LOS_BATCH_TILE_MB", "2")

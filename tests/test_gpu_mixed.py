@@ -106,10 +106,10 @@ def test_mixed_small_vs_oracle(torch_dev, ctx, cfg, prec):
     assert worst <= 1.0, (prec, worst, cerr)
 
 
-@pytest.mark.parametrize("mb,nc", [(1, 1), (2, 1), (2, 2), (4, 4)])
+@pytest.mark.parametrize("mb,nc", [(1, 1), (2, 1), (2, 2), (4, 4), (16, 8)])
 def test_mixed_tiles_agree(torch_dev, ctx, mb, nc, monkeypatch):
-    """Every compiled tile shape gives the same Delta (bitwise: the tau order of the
-    accumulation does not depend on the tile)."""
+    """Every compiled tile shape, including the LDS-staged 256 x 128 kernel, gives the same
+    Delta (bitwise: the tau order of the accumulation does not depend on the tile)."""
     wl = inputs.small(lmax=150, nk=6, kmax=0.05, ntau=700, nsrc=3)
     base, _, _ = run_mixed(torch_dev, ctx, wl, 2)
     monkeypatch.setenv("LOS_GEMM_MB", str(mb))
