@@ -46,6 +46,13 @@ def tp_and_band_counts(wl):
     return tp, band
 
 
+def fp64_kernel():
+    """(kernel name, source file) of the FP64 projection los_project launches."""
+    if os.environ.get("LOS_PROJ_SCHEME", "1").strip() == "0":
+        return "project_fp64_kernel", "project_fp64.hip"
+    return "project_fp64_desc_kernel", "project_fp64_desc.hip"
+
+
 def traffic_for(prec, wl):
     """HBM bytes per projection launch from the committed counter profile of the same kernel
     source and workload (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
@@ -53,8 +60,9 @@ def traffic_for(prec, wl):
     import hashlib
     if prec != 0:
         return None
-    path = os.path.join(ROOT, "profiles", "project_fp64_%s.txt" % wl.name)
-    src = os.path.join(ROOT, "paper_2509_25110_amd", "csrc", "project_fp64.hip")
+    name, fname = fp64_kernel()
+    path = os.path.join(ROOT, "profiles", "%s_%s.txt" % (name.replace("_kernel", ""), wl.name))
+    src = os.path.join(ROOT, "paper_2509_25110_amd", "csrc", fname)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -320,7 +328,25 @@ def run_emulator(args):
     ref = cte.cpu().numpy()
     scale = np.abs(ref).copy()
     scale[:, 2] = np.sqrt(ref[:, 0] * ref[:, 1])
-    true_err = np.max(np.abs(c - ref) / scale, axis=(1, 2))
+    rel = np.abs(c - ref) / scale
+    true_err = np.max(rel, axis=(1, 2))
+    # where the error sits: per spectrum, and below l = 2500
+    per_spec = {nm: float(np.median(np.max(rel[:, i], axis=1)))
+                for i, nm in enumerate(("TT", "EE", "TE", "PP"))}
+    low_l = float(np.median(np.max(rel[:, :, :2499], axis=(1, 2))))
+    # PCA truncation alone: held-out spectra projected on the emulator's basis
+    pca = emu.emu_get_pca()
+    t = pca["te_scale"]
+    y = np.empty_like(ref)
+    y[:, 0], y[:, 1], y[:, 3] = np.log(ref[:, 0]), np.log(ref[:, 1]), np.log(ref[:, 3])
+    y[:, 2] = np.arcsinh(ref[:, 2] / t)
+    yr = np.empty_like(y)
+    for sp in range(4):
+        B = pca["basis"][sp]
+        yr[:, sp] = pca["mean"][sp] + ((y[:, sp] - pca["mean"][sp]) @ B) @ B.T
+    cr = np.exp(yr)
+    cr[:, 2] = t * np.sinh(yr[:, 2])
+    trunc_err = np.max(np.abs(cr - ref) / scale, axis=(1, 2))
     # inference throughput at batch 4096 (held-out parameters repeated)
     P = dv(np.repeat(pte, 16, axis=0))
     cl_buf = torch.empty((P.shape[0], 4, nl), dtype=torch.float64, device="cuda")
@@ -373,6 +399,10 @@ def run_emulator(args):
         "heldout_err_p90": float(np.quantile(true_err, 0.9)),
         "heldout_err_max": float(true_err.max()),
         "estimate_over_true_median": float(np.median(err / true_err)),
+        "heldout_err_median_per_spectrum": per_spec,
+        "heldout_err_median_l_below_2500": low_l,
+        "pca_truncation_err_median": float(np.median(trunc_err)),
+        "logTT_range_at_lmax": float(np.ptp(y[:, 0, -1])),
         "fallback_threshold": thr, "fallback_fraction": frac,
         "effective_spectra_per_s_with_fallback": effective,
         "batch_solver_spectra_per_s": solve_rate,
@@ -476,7 +506,7 @@ def main():
     err = golden_error(cl.cpu().numpy(), wl)
 
     path = {0: "FP64 plain path", 1: "FP32 MFMA path", 2: "split-BF16x3 MFMA path"}[prec]
-    kernel = "project_fp64_kernel" if prec == 0 else "jtable_kernel + mfma_gemm_kernel"
+    kernel = fp64_kernel()[0] if prec == 0 else "jtable_kernel + mfma_gemm_kernel"
     out = {
         "metric": METRIC,
         "value": K / (total_ms * 1e-3),

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblos.so")
 
-SOURCES = ["los_api.cpp", "bessel_table.hip", "project_fp64.hip", "cl_reduce.hip", "jtable.hip",
+SOURCES = ["los_api.cpp", "bessel_table.hip", "project_fp64.hip", "project_fp64_desc.hip", "cl_reduce.hip", "jtable.hip",
            "project_mfma.hip", "project_mfma_lds.hip", "batch_cl.hip", "batch_api.cpp", "emu_kernels.hip", "emu_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -238,8 +238,15 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
     return project_mixed(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S, nsrc,
                          prec, (float *)delta, (hipStream_t)stream);
 
+  // Default: the single descending sweep; LOS_PROJ_SCHEME=0 selects the
+  // two-pass kernel (ascending upward, then descending Miller).
+  const char *scheme = std::getenv("LOS_PROJ_SCHEME");
+  const bool desc = !(scheme && std::atoi(scheme) == 0);
   los::ProjectShape sh =
-      los::project_fp64_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"), env_int("LOS_PROJ_SLOTS"));
+      desc ? los::project_fp64_desc_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"),
+                                          env_int("LOS_PROJ_SLOTS"))
+           : los::project_fp64_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"),
+                                     env_int("LOS_PROJ_SLOTS"));
   if (sh.waves == 0)
     return fail(LOS_ERR_UNSUPPORTED, "los_project: no launch shape for ntau = %lld",
                 (long long)ntau);
@@ -258,7 +265,8 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
   a.w = w_tau;
   a.S = (const double *)S;
   a.delta = (double *)delta;
-  hipError_t e = los::project_fp64_launch(a, nsrc, sh, (hipStream_t)stream);
+  hipError_t e = desc ? los::project_fp64_desc_launch(a, nsrc, sh, (hipStream_t)stream)
+                      : los::project_fp64_launch(a, nsrc, sh, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "los_project launch");
   return ok();
 }

@@ -32,6 +32,11 @@ struct ProjectShape {
 ProjectShape project_fp64_shape(int nsrc, int64_t ntau, int force_waves = 0, int force_slots = 0);
 hipError_t project_fp64_launch(const ProjectArgs &a, int nsrc, const ProjectShape &sh,
                                hipStream_t s);
+// Single descending sweep variant (project_fp64_desc.hip), same arguments.
+ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves = 0,
+                                     int force_slots = 0);
+hipError_t project_fp64_desc_launch(const ProjectArgs &a, int nsrc, const ProjectShape &sh,
+                                    hipStream_t s);
 
 // Weighted Bessel tables for the MFMA projection (see jtable.hip):
 // J[(kc*nlp + l - lmin)*ntp + n] = w_n j_l(k[k0 + kc] (tau0 - tau_n)) in FP32,

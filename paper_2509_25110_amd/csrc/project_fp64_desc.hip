@@ -1,0 +1,281 @@
+// FP64 line-of-sight projection, single descending sweep (gCAMB paper
+// Sec. 2.1 Eq. 2-3; Sec. 3.2 / Algorithm 1 for the k / l / tau loops):
+//
+//   delta[k][l][s] = sum_n w_n S[s][k][n] j_l(k (tau0 - tau_n))
+//
+// Same workgroup / wave / slot mapping and per-block reduction as
+// project_fp64.hip, but every lane walks its l range once, from the top down:
+//   * setup: each node finds w (j_R, j_{R+1}) at its top row
+//     R = min(ltop(x), lmax).  For x >= lmax + 1 the upward recurrence from
+//     j_{-1} = cos x / x, j_0 = sin x / x runs to lmax + 1 (stable on the
+//     oscillatory side); otherwise it runs to m = floor(x) for j_m, and
+//     Miller's recurrence from ltop(x) with seeds (0, 1) runs down to m and is
+//     scaled there to j_m (j_m is near the last maximum in l, never near a
+//     zero), giving the pair at R;
+//   * the sweep: blocks of B = 8 rows from the highest top of the workgroup
+//     down to lmin; each lane runs j_{l-1} = (2l+1)/x j_l - j_{l+1} for its
+//     slots, rows above its R contributing 0.  Downward is the stable
+//     direction above the turning point and neutrally stable below it, so one
+//     sweep covers the whole band with no second pass and no read-modify-write
+//     of delta.
+#include "bessel_dev.hpp"
+#include "fp64_common.hpp"
+#include "los_internal.hpp"
+
+#include <climits>
+
+namespace los {
+namespace {
+
+using fp64::has;
+using fp64::load_s;
+using fp64::slot_mask;
+using fp64::wave_max;
+using fp64::wave_min;
+using fp64::wg_reduce;
+
+// One slot over the block of rows top .. top-B+1, descending.  (p1, p0) =
+// (w j_{l+1}, w j_l) at l = top on entry.  With MASK, only rows l <= R are
+// live (rel = R - (top - B + 1)); the others output 0 and leave the state.
+template <int NSRC, int B, bool MASK>
+__device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, double &p0,
+                                           double ix, const double (&sv)[NSRC], int top, int rel) {
+  double t = (double)(2 * top + 1) * ix;
+  const double d2 = ix + ix;
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    // row l = top - i is live when l <= R, i.e. i >= top - R = (B - 1) - rel
+    const int q = (B - 1 - i) * NSRC;
+    if (MASK) {
+      const bool live = i >= (B - 1) - rel;
+      const double o = live ? p0 : 0.0;
+#pragma unroll
+      for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(o, sv[s], acc[q + s]);
+      const double nx = rec_step(t, p0, p1);
+      p1 = live ? p0 : p1;
+      p0 = live ? nx : p0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
+      const double nx = rec_step(t, p0, p1);
+      p1 = p0;
+      p0 = nx;
+    }
+    t -= d2;
+  }
+}
+
+template <int NSRC, int T>
+__global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
+  constexpr int B = kProjectBlock;
+  constexpr int NV = B * NSRC;
+  extern __shared__ double lds[];
+
+  const int W = blockDim.x >> 6;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t ki = a.nk - 1 - (int64_t)blockIdx.x;  // large k (most work) first
+  const int lmin = a.lmin, lmax = a.lmax;
+  const int ntau = (int)a.ntau;
+  const int npad = W * 64 * T;
+
+  double *ixs = lds;                                  // [npad] 1/x per node
+  int *rs = (int *)(lds + npad);                      // [npad] top row R per node (-1: none)
+  double *const lds2 = lds + npad + (npad + 1) / 2;
+  double *stage = lds2 + w * NV * 16;                 // per wave [NV][16]
+  double *cross0 = lds2 + W * NV * 16;                // [2][W][NV]
+  int *bnd = (int *)(cross0 + 2 * W * NV);            // [1]
+
+  const double kk = a.k[ki];
+  const double *srow[NSRC];
+#pragma unroll
+  for (int s = 0; s < NSRC; ++s) srow[s] = a.S + ((int64_t)s * a.nk + ki) * a.ntau;
+
+  // ---------------- per-node setup: the pair at the top row ----------------
+  double Jn[T], Jc[T];  // w j_{l+1}, w j_l of the current row, per slot
+  // Per-slot block thresholds held by lane j for slot j (wave-uniform):
+  // the slot runs unmasked in blocks bi <= thF and at all in blocks bi <= thA.
+  int thF = -1, thA = -1, my_top = -1;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const int n = (w + W * j) * 64 + lane;
+    int R = -1;
+    double ix = 0.0, cur = 0.0, nxt = 0.0;
+    if (n < ntau) {
+      const double x = kk * (a.tau0 - a.tau[n]);
+      const double wn = a.w[n];
+      if (x >= kXTiny && wn != 0.0) {
+        ix = 1.0 / x;
+        double sn, cs;
+        sincos(x, &sn, &cs);
+        double p = wn * (cs * ix), q = wn * (sn * ix);  // w j_{-1}, w j_0
+        const double fx = floor(x);
+        // coefficients (2l+1)/x are formed exactly at every step of the long
+        // setup runs (a running sum would drift by up to ~lmax ulps)
+        if (fx >= (double)(lmax + 1)) {
+          for (int l = 0; l <= lmax; ++l) {
+            const double r = rec_step((double)(2 * l + 1) * ix, q, p);
+            p = q;
+            q = r;
+          }
+          R = lmax;
+          cur = p;  // w j_lmax
+          nxt = q;  // w j_{lmax+1}
+        } else {
+          const int m = (int)fx;
+          for (int l = 0; l < m; ++l) {
+            const double r = rec_step((double)(2 * l + 1) * ix, q, p);
+            p = q;
+            q = r;
+          }
+          const double jm = q;  // w j_m
+          const int L0 = ltop_of(x);
+          R = L0 < lmax ? L0 : lmax;
+          double hn = 0.0, hc = 1.0, hR = 1.0, hR1 = 0.0;  // Miller from (0, 1) at L0
+          for (int l = L0; l > m; --l) {
+            const double hp = rec_step((double)(2 * l + 1) * ix, hc, hn);
+            hn = hc;
+            hc = hp;
+            if (l - 1 == R) {
+              hR = hc;
+              hR1 = hn;
+            }
+          }
+          const double sc = jm / hc;
+          cur = sc * hR;
+          nxt = sc * hR1;
+        }
+        if (R < lmin) R = -1;
+      }
+    }
+    ixs[n] = ix;
+    rs[n] = R;
+    Jc[j] = cur;
+    Jn[j] = nxt;
+    // wave-uniform thresholds of this slot
+    const int rmax = wave_max(R), rmin = wave_min(R >= 0 ? R : -1);
+    // unmasked in block bi when every lane's R >= top of the block = lmin + 8 bi + 7
+    const int f = rmin - lmin - (B - 1) >= 0 ? (rmin - lmin - (B - 1)) / B : -1;
+    const int ab = rmax >= lmin ? (rmax - lmin) / B : -1;
+    if (lane == j) {
+      thF = f;
+      thA = ab;
+    }
+    my_top = ab > my_top ? ab : my_top;
+  }
+  if (threadIdx.x == 0) bnd[0] = -1;
+  __syncthreads();
+  atomicMax(&bnd[0], my_top);
+  __syncthreads();
+  const int top_blk = bnd[0];
+
+  double *drow = a.delta + ki * (int64_t)a.nl * NSRC;
+  // blocks above every lane's top row are zero
+  if (w == 0 && lane < NV) {
+    for (int bi = top_blk + 1; bi < a.nblk; ++bi) {
+      const int b = lmin + bi * B;
+      if (b + lane / NSRC <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] = 0.0;
+    }
+  }
+  int parity = 0;
+  for (int bi = top_blk; bi >= 0; --bi) {
+    const int b = lmin + bi * B;
+    const int top = b + B - 1;
+    const uint64_t fm = slot_mask(thF >= bi);        // all lanes live through the block
+    const uint64_t pm = slot_mask(thA >= bi) & ~fm;  // some lanes start inside it
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    {
+      double sv[NSRC], svn[NSRC];
+      load_s<NSRC>(sv, srow, w * 64 + lane, ntau);
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        const int nb = (w + W * j) * 64;
+        if (nb >= ntau) break;
+        int n = nb + lane;
+        asm volatile("" : "+v"(n));
+        if (j + 1 < T) load_s<NSRC>(svn, srow, n + W * 64, ntau);
+        if (has(fm, j)) sweep_slot<NSRC, B, false>(acc, Jn[j], Jc[j], ixs[n], sv, top, 0);
+#pragma unroll
+        for (int s = 0; s < NSRC; ++s) sv[s] = svn[s];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      const int nb = (w + W * j) * 64;
+      if (nb >= ntau) break;
+      int n = nb + lane;
+      asm volatile("" : "+v"(n));
+      if (has(pm, j)) {
+        double sv[NSRC];
+        load_s<NSRC>(sv, srow, n, ntau);
+        int rel = rs[n] - b;  // rows b .. b + rel are live (rel < 0: none)
+        asm volatile("" : "+v"(rel));
+        sweep_slot<NSRC, B, true>(acc, Jn[j], Jc[j], ixs[n], sv, top, rel);
+      }
+    }
+    const double tot = wg_reduce<NV>(acc, stage, cross0 + parity * W * NV, W, w, lane);
+    parity ^= 1;
+    if (w == 0 && lane < NV) {
+      const int l = b + lane / NSRC;
+      if (l <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] = tot;
+    }
+  }
+}
+
+template <int NSRC, int T>
+hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
+  auto kern = project_fp64_desc_kernel<NSRC, T>;
+  if (sh.lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.nk), dim3(64 * sh.waves), sh.lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NSRC>
+hipError_t launch_n(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
+  switch (sh.slots) {
+    case 4: return launch_t<NSRC, 4>(a, sh, s);
+    case 8: return launch_t<NSRC, 8>(a, sh, s);
+    case 12: return launch_t<NSRC, 12>(a, sh, s);
+    case 16: return launch_t<NSRC, 16>(a, sh, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves, int force_slots) {
+  ProjectShape sh{};
+  int W = force_waves > 0 ? force_waves : (int)((ntau + 64 * 12 - 1) / (64 * 12));
+  if (W < 1) W = 1;
+  if (W > 8) return sh;
+  int T = force_slots > 0 ? force_slots : (int)((ntau + 64 * W - 1) / (64 * W));
+  T = (T + 3) / 4 * 4;
+  if (T < 4) T = 4;
+  if (T > 16 || (int64_t)64 * W * T < ntau) return sh;  // waves == 0: unsupported
+  sh.waves = W;
+  sh.slots = T;
+  const int NV = kProjectBlock * nsrc;
+  const int npad = W * 64 * T;
+  sh.lds = sizeof(double) * ((size_t)npad + (size_t)(npad + 1) / 2 + (size_t)W * NV * 16 +
+                            2 * (size_t)W * NV) +
+           4 * sizeof(int);
+  return sh;
+}
+
+hipError_t project_fp64_desc_launch(const ProjectArgs &a, int nsrc, const ProjectShape &sh,
+                                    hipStream_t s) {
+  switch (nsrc) {
+    case 1: return launch_n<1>(a, sh, s);
+    case 2: return launch_n<2>(a, sh, s);
+    case 3: return launch_n<3>(a, sh, s);
+    case 4: return launch_n<4>(a, sh, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace los

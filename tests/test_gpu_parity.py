@@ -145,7 +145,7 @@ def test_project_c1_full(torch_dev, ctx):
     check_workload(torch_dev, ctx, inputs.config("C1"))
 
 
-@pytest.mark.parametrize("waves,slots", [(1, 12), (2, 8), (4, 4), (3, 12), (5, 4)])
+@pytest.mark.parametrize("waves,slots", [(1, 12), (2, 8), (4, 4), (3, 12), (5, 4), (1, 16)])
 def test_project_launch_shapes_agree(torch_dev, ctx, waves, slots, monkeypatch):
     torch = torch_dev
     wl = inputs.small(lmax=140, nk=6, kmax=0.05, ntau=700, nsrc=3)
@@ -245,3 +245,41 @@ def test_c2_full_size_sampled(torch_dev, ctx):
     for r, ref in zip(rows, refs):
         err = np.max(np.abs(d[r] - ref) / scale)
         assert err <= 1e-10, (r, err)
+
+
+# ---------------------------------------------------------------- two-pass kernel
+
+@pytest.mark.parametrize("cfg", SMALL, ids=[str(i) for i in range(len(SMALL))])
+def test_twopass_scheme_small_vs_oracle(torch_dev, ctx, cfg, monkeypatch):
+    """The two-pass kernel (LOS_PROJ_SCHEME=0: ascending upward, descending Miller) meets the
+    same 1e-10 bounds as the default single descending sweep."""
+    monkeypatch.setenv("LOS_PROJ_SCHEME", "0")
+    cfg = dict(cfg)
+    nsrc = cfg.pop("nsrc")
+    wl = inputs.small(nsrc=min(nsrc, 3), **cfg)
+    if nsrc == 4:
+        rng = np.random.default_rng(11)
+        wl.S = np.concatenate([wl.S, rng.normal(size=(1, wl.nk, wl.ntau)) * wl.S[:1]], axis=0)
+        wl.pairs = inputs.PAIRS_4 + ((3, 3), (0, 3))
+    check_workload(torch_dev, ctx, wl)
+
+
+def test_twopass_scheme_edge_cases_and_c1(torch_dev, ctx, monkeypatch):
+    monkeypatch.setenv("LOS_PROJ_SCHEME", "0")
+    torch = torch_dev
+    for lmin, lmax, nk, ntau in [(2, 2, 1, 5), (37, 37, 3, 129), (2, 9, 4, 64), (150, 160, 3, 200)]:
+        wl = inputs.small(lmax=lmax, nk=nk, kmax=0.05, ntau=ntau, nsrc=3)
+        wl.lmin = lmin
+        d, _ = run_gpu(torch, ctx, wl)
+        ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S,
+                                with_abs=True)
+        assert_delta_normwise(d, ref, A)
+    check_workload(torch, ctx, inputs.config("C1"))
+    wl = inputs.small(lmax=50, nk=5, kmax=1e-3, ntau=64, nsrc=3)
+    check_workload(torch, ctx, wl, cut_floor=1e-18)
+
+
+def test_twopass_scheme_c2_full_size_sampled(torch_dev, ctx, monkeypatch):
+    """C2 at full size with the two-pass kernel: golden C_l and sampled Delta rows at 1e-10."""
+    monkeypatch.setenv("LOS_PROJ_SCHEME", "0")
+    test_c2_full_size_sampled(torch_dev, ctx)
