@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -244,7 +245,8 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
   const bool desc = !(scheme && std::atoi(scheme) == 0);
   los::ProjectShape sh =
       desc ? los::project_fp64_desc_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"),
-                                          env_int("LOS_PROJ_SLOTS"))
+                                          env_int("LOS_PROJ_SLOTS"), env_int("LOS_PROJ_BLOCK"),
+                                          (size_t)std::max(0, env_int("LOS_PROJ_LDS_EXTRA")))
            : los::project_fp64_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"),
                                      env_int("LOS_PROJ_SLOTS"));
   if (sh.waves == 0)

@@ -22,9 +22,10 @@ struct ProjectArgs {
 
 // Launch shape chosen by the host for the FP64 projection.
 struct ProjectShape {
-  int waves;   // waves per workgroup (1..8)
-  int slots;   // tau slots per lane (4, 8, 12, 16)
-  size_t lds;  // dynamic LDS bytes
+  int waves;      // waves per workgroup (1..8)
+  int slots;      // tau slots per lane (4, 8, 12, 16)
+  size_t lds;     // dynamic LDS bytes
+  int block = 8;  // l rows per block (descending sweep: 8 or 16)
 };
 
 // FP64 projection: one workgroup per k.
@@ -33,8 +34,10 @@ ProjectShape project_fp64_shape(int nsrc, int64_t ntau, int force_waves = 0, int
 hipError_t project_fp64_launch(const ProjectArgs &a, int nsrc, const ProjectShape &sh,
                                hipStream_t s);
 // Single descending sweep variant (project_fp64_desc.hip), same arguments.
+// block: 8 or 16 (default, also for 0) rows per reduction; lds_extra:
+// additional LDS per workgroup (bounds the workgroups per CU).
 ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves = 0,
-                                     int force_slots = 0);
+                                     int force_slots = 0, int block = 8, size_t lds_extra = 0);
 hipError_t project_fp64_desc_launch(const ProjectArgs &a, int nsrc, const ProjectShape &sh,
                                     hipStream_t s);
 

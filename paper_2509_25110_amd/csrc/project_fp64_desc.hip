@@ -12,8 +12,8 @@
 //     Miller's recurrence from ltop(x) with seeds (0, 1) runs down to m and is
 //     scaled there to j_m (j_m is near the last maximum in l, never near a
 //     zero), giving the pair at R;
-//   * the sweep: blocks of B = 8 rows from the highest top of the workgroup
-//     down to lmin; each lane runs j_{l-1} = (2l+1)/x j_l - j_{l+1} for its
+//   * the sweep: blocks of B = 16 rows (8 selectable) from the highest top of
+//     the workgroup down to lmin; each lane runs j_{l-1} = (2l+1)/x j_l - j_{l+1} for its
 //     slots, rows above its R contributing 0.  Downward is the stable
 //     direction above the turning point and neutrally stable below it, so one
 //     sweep covers the whole band with no second pass and no read-modify-write
@@ -40,10 +40,13 @@ using fp64::wg_reduce;
 template <int NSRC, int B, bool MASK>
 __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, double &p0,
                                            double ix, const double (&sv)[NSRC], int top, int rel) {
-  double t = (double)(2 * top + 1) * ix;
+  double t = 0.0;
   const double d2 = ix + ix;
 #pragma unroll
   for (int i = 0; i < B; ++i) {
+    // the coefficient (2l+1)/x is formed exactly every 8 rows and stepped by
+    // -2/x in between (at most 7 rounding steps, whatever the block size)
+    if (i % 8 == 0) t = (double)(2 * (top - i) + 1) * ix;
     // row l = top - i is live when l <= R, i.e. i >= top - R = (B - 1) - rel
     const int q = (B - 1 - i) * NSRC;
     if (MASK) {
@@ -65,10 +68,10 @@ __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, 
   }
 }
 
-template <int NSRC, int T>
+template <int NSRC, int T, int B>
 __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
-  constexpr int B = kProjectBlock;
   constexpr int NV = B * NSRC;
+  const int nblk = (a.nl + B - 1) / B;
   extern __shared__ double lds[];
 
   const int W = blockDim.x >> 6;
@@ -171,7 +174,7 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   double *drow = a.delta + ki * (int64_t)a.nl * NSRC;
   // blocks above every lane's top row are zero
   if (w == 0 && lane < NV) {
-    for (int bi = top_blk + 1; bi < a.nblk; ++bi) {
+    for (int bi = top_blk + 1; bi < nblk; ++bi) {
       const int b = lmin + bi * B;
       if (b + lane / NSRC <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] = 0.0;
     }
@@ -223,9 +226,9 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   }
 }
 
-template <int NSRC, int T>
+template <int NSRC, int T, int B>
 hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
-  auto kern = project_fp64_desc_kernel<NSRC, T>;
+  auto kern = project_fp64_desc_kernel<NSRC, T, B>;
   if (sh.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
@@ -235,21 +238,28 @@ hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s)
   return hipGetLastError();
 }
 
-template <int NSRC>
-hipError_t launch_n(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
+template <int NSRC, int B>
+hipError_t launch_b(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
   switch (sh.slots) {
-    case 4: return launch_t<NSRC, 4>(a, sh, s);
-    case 8: return launch_t<NSRC, 8>(a, sh, s);
-    case 12: return launch_t<NSRC, 12>(a, sh, s);
-    case 16: return launch_t<NSRC, 16>(a, sh, s);
+    case 4: return launch_t<NSRC, 4, B>(a, sh, s);
+    case 8: return launch_t<NSRC, 8, B>(a, sh, s);
+    case 12: return launch_t<NSRC, 12, B>(a, sh, s);
+    case 16: return launch_t<NSRC, 16, B>(a, sh, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+template <int NSRC>
+hipError_t launch_n(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
+  return sh.block == 16 ? launch_b<NSRC, 16>(a, sh, s) : launch_b<NSRC, 8>(a, sh, s);
+}
+
 }  // namespace
 
-ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves, int force_slots) {
+ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves, int force_slots,
+                                     int block, size_t lds_extra) {
   ProjectShape sh{};
+  sh.block = block == 8 ? 8 : 16;  // 16 rows per reduction halves the source reloads
   int W = force_waves > 0 ? force_waves : (int)((ntau + 64 * 12 - 1) / (64 * 12));
   if (W < 1) W = 1;
   if (W > 8) return sh;
@@ -259,11 +269,11 @@ ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves, in
   if (T > 16 || (int64_t)64 * W * T < ntau) return sh;  // waves == 0: unsupported
   sh.waves = W;
   sh.slots = T;
-  const int NV = kProjectBlock * nsrc;
+  const int NV = sh.block * nsrc;
   const int npad = W * 64 * T;
   sh.lds = sizeof(double) * ((size_t)npad + (size_t)(npad + 1) / 2 + (size_t)W * NV * 16 +
                             2 * (size_t)W * NV) +
-           4 * sizeof(int);
+           4 * sizeof(int) + lds_extra;
   return sh;
 }
 

@@ -283,3 +283,12 @@ def test_twopass_scheme_c2_full_size_sampled(torch_dev, ctx, monkeypatch):
     """C2 at full size with the two-pass kernel: golden C_l and sampled Delta rows at 1e-10."""
     monkeypatch.setenv("LOS_PROJ_SCHEME", "0")
     test_c2_full_size_sampled(torch_dev, ctx)
+
+
+@pytest.mark.parametrize("cfg", [SMALL[0], SMALL[3], SMALL[4]], ids=["0", "3", "4"])
+def test_sweep_block8_small_vs_oracle(torch_dev, ctx, cfg, monkeypatch):
+    """The descending sweep with 8-row blocks (LOS_PROJ_BLOCK=8; the default is 16)."""
+    monkeypatch.setenv("LOS_PROJ_BLOCK", "8")
+    cfg = dict(cfg)
+    nsrc = cfg.pop("nsrc")
+    check_workload(torch_dev, ctx, inputs.small(nsrc=min(nsrc, 3), **cfg))
