@@ -59,27 +59,33 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
       double s, c;
       sincos(x, &s, &c);
       double p = c * ix, q = s * ix;  // j_{l-1}, j_l at l = 0
-      if (m >= a.lmax + 1) {
-        for (int l = 0; l <= a.lmax; ++l) {
-          const double r = rec_step((double)(2 * l + 1) * ix, q, p);
+      // coefficient (2l+1)/x formed exactly every 8 steps, stepped by 2/x between
+      const double d2 = ix + ix;
+      const int up = m >= a.lmax + 1 ? a.lmax + 1 : m;
+      {
+        double t = ix;
+        for (int l = 0; l < up; ++l) {
+          if ((l & 7) == 0) t = (double)(2 * l + 1) * ix;
+          const double r = rec_step(t, q, p);
+          t += d2;
           p = q;
           q = r;
         }
+      }
+      if (m >= a.lmax + 1) {
         R = a.lmax;
         cur = wt * p;
         nxt = wt * q;
       } else {
-        for (int l = 0; l < m; ++l) {
-          const double r = rec_step((double)(2 * l + 1) * ix, q, p);
-          p = q;
-          q = r;
-        }
         const double jm = q;
         R = min(L0, a.lmax);
         double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l at l = L0
         double hR = 1.0, hR1 = 0.0;
+        double t = 0.0;
         for (int l = L0; l > m; --l) {
-          const double hp = rec_step((double)(2 * l + 1) * ix, hc, hn);
+          if (((L0 - l) & 7) == 0) t = (double)(2 * l + 1) * ix;
+          const double hp = rec_step(t, hc, hn);
+          t -= d2;
           hn = hc;
           hc = hp;
           if (l - 1 == R) {
@@ -108,16 +114,19 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
   for (int b = tb_wave; b >= 0; --b) {
     const int lbase = a.lmin + 16 * b;
     float *dst = col + (int64_t)(16 * b) * a.ntp;
+    double t = 0.0;
 #pragma unroll
     for (int r = 15; r >= 0; --r) {
       const int l = lbase + r;
+      if (r == 15 || r == 7) t = (double)(2 * l + 1) * ix;  // exact every 8 rows
       float v = 0.f;
       if (l <= R) {
         v = (float)cur;
-        const double pv = rec_step((double)(2 * l + 1) * ix, cur, nxt);
+        const double pv = rec_step(t, cur, nxt);
         nxt = cur;
         cur = pv;
       }
+      t -= ix + ix;
       dst[(int64_t)r * a.ntp] = v;
     }
   }

@@ -112,33 +112,48 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         sincos(x, &sn, &cs);
         double p = wn * (cs * ix), q = wn * (sn * ix);  // w j_{-1}, w j_0
         const double fx = floor(x);
-        // coefficients (2l+1)/x are formed exactly at every step of the long
-        // setup runs (a running sum would drift by up to ~lmax ulps)
-        if (fx >= (double)(lmax + 1)) {
-          for (int l = 0; l <= lmax; ++l) {
-            const double r = rec_step((double)(2 * l + 1) * ix, q, p);
+        // upward runs: the coefficient (2l+1)/x is formed exactly every 8
+        // steps and stepped by 2/x in between (at most 7 rounding steps)
+        const double d2 = ix + ix;
+        const int up = fx >= (double)(lmax + 1) ? lmax + 1 : (int)fx;
+        int l = 0;
+        for (; l + 8 <= up; l += 8) {
+          double t = (double)(2 * l + 1) * ix;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const double r = rec_step(t, q, p);
+            t += d2;
             p = q;
             q = r;
           }
+        }
+        {
+          double t = (double)(2 * l + 1) * ix;
+          for (; l < up; ++l) {
+            const double r = rec_step(t, q, p);
+            t += d2;
+            p = q;
+            q = r;
+          }
+        }
+        if (fx >= (double)(lmax + 1)) {
           R = lmax;
           cur = p;  // w j_lmax
           nxt = q;  // w j_{lmax+1}
         } else {
-          const int m = (int)fx;
-          for (int l = 0; l < m; ++l) {
-            const double r = rec_step((double)(2 * l + 1) * ix, q, p);
-            p = q;
-            q = r;
-          }
+          const int m = up;
           const double jm = q;  // w j_m
           const int L0 = ltop_of(x);
           R = L0 < lmax ? L0 : lmax;
           double hn = 0.0, hc = 1.0, hR = 1.0, hR1 = 0.0;  // Miller from (0, 1) at L0
-          for (int l = L0; l > m; --l) {
-            const double hp = rec_step((double)(2 * l + 1) * ix, hc, hn);
+          double t = (double)(2 * L0 + 1) * ix;
+          for (int ll = L0; ll > m; --ll) {
+            if (((L0 - ll) & 7) == 0) t = (double)(2 * ll + 1) * ix;
+            const double hp = rec_step(t, hc, hn);
+            t -= d2;
             hn = hc;
             hc = hp;
-            if (l - 1 == R) {
+            if (ll - 1 == R) {
               hR = hc;
               hR1 = hn;
             }
