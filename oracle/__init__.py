@@ -11,7 +11,9 @@ integrals) and Sec. 3.2 / Algorithm 1 (loop over k, then l, then tau):
 
 * :func:`sph_jl`        -- j_l(x), l = 0..lmax (spherical Bessel kernel, flat space)
 * :func:`bessel_table`  -- j_l(x_i) as an [l - lmin][i] table
-* :func:`project`       -- Delta^X_l(k_i) = sum_n w_n S_X(k_i, tau_n) j_l(k_i (tau0 - tau_n))
+* :func:`eps_l`         -- the E-mode kernel sqrt((l+2)!/(l-2)!) j_l(x)/x^2 (Eq. 3)
+* :func:`project`       -- Delta^X_l(k_i) = sum_n w_n S_X(k_i, tau_n) K_l(k_i (tau0 - tau_n)),
+                           K = j_l, or eps_l for the sources selected by a mask
 * :func:`cl`            -- C^XY_l = 4 pi sum_i w_i P(k_i) Delta^X_l(k_i) Delta^Y_l(k_i)
 """
 from __future__ import annotations
@@ -57,12 +59,19 @@ def _load():
                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                 _c_double_p, _c_double_p, _c_double_p, _c_double_p, ctypes.c_int32,
                 _c_double_p, _c_double_p]
+            lib.oracle_project_kernels.argtypes = [
+                ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                _c_double_p, _c_double_p, _c_double_p, _c_double_p, ctypes.c_int32,
+                ctypes.c_uint32, _c_double_p, _c_double_p]
+            lib.oracle_eps_l.argtypes = [ctypes.c_int32, ctypes.c_double, _c_double_p,
+                                         _c_double_p]
             lib.oracle_cl.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _c_double_p,
                                       _c_double_p, _c_double_p, _c_int32_p, ctypes.c_int32,
                                       _c_double_p]
             lib.oracle_num_threads.argtypes = []
             for f in (lib.oracle_sph_jl, lib.oracle_bessel_table, lib.oracle_project,
-                      lib.oracle_cl, lib.oracle_num_threads):
+                      lib.oracle_project_kernels, lib.oracle_eps_l, lib.oracle_cl,
+                      lib.oracle_num_threads):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -99,13 +108,24 @@ def bessel_table(x, lmin: int, lmax: int) -> np.ndarray:
     return out
 
 
-def project(lmin, lmax, k, tau, tau0, w_tau, S, with_abs=False, k_range=None):
+def eps_l(lmax, x) -> np.ndarray:
+    """E-mode kernel eps_l(x) = sqrt((l+2)!/(l-2)!) j_l(x) / x^2 for l = 0..lmax (Sec. 2.1,
+    Eq. 3); 0 for l < 2; the x -> 0 limit is sqrt(24)/15 at l = 2 and 0 above."""
+    jl = np.empty(lmax + 1)
+    out = np.empty(lmax + 1)
+    _check(_load().oracle_eps_l(int(lmax), float(x), jl.ctypes.data_as(_c_double_p),
+                                out.ctypes.data_as(_c_double_p)), "eps_l")
+    return out
+
+
+def project(lmin, lmax, k, tau, tau0, w_tau, S, with_abs=False, k_range=None, eps_mask=0):
     """LOS projection (Eq. 2-3).
 
     ``S`` is [nsrc, nk, ntau]; returns delta [nk, nl, nsrc] (and the absolute
     sum ``A`` of the same shape if ``with_abs``).  ``k_range=(a, b)`` computes
     only rows a..b-1 and returns arrays of b - a rows (each row depends only on
-    its own k and S row, so this equals slicing the full result).
+    its own k and S row, so this equals slicing the full result).  Sources whose
+    bit is set in ``eps_mask`` use the E-mode kernel eps_l instead of j_l.
     """
     S = np.asarray(S)
     k = np.asarray(k)
@@ -122,8 +142,8 @@ def project(lmin, lmax, k, tau, tau0, w_tau, S, with_abs=False, k_range=None):
     nl = lmax - lmin + 1
     delta = np.empty((nk, nl, nsrc))
     absd = np.empty((nk, nl, nsrc)) if with_abs else None
-    rc = _load().oracle_project(
-        int(lmin), int(lmax), nk, ntau, float(tau0), kp, tp, wp, sp, nsrc,
+    rc = _load().oracle_project_kernels(
+        int(lmin), int(lmax), nk, ntau, float(tau0), kp, tp, wp, sp, nsrc, int(eps_mask),
         delta.ctypes.data_as(_c_double_p),
         absd.ctypes.data_as(_c_double_p) if with_abs else None)
     _check(rc, "project")

@@ -168,14 +168,52 @@ int oracle_bessel_table(const double *x, int64_t nx, int32_t lmin, int32_t lmax,
 }
 
 /*
- * Eq. 2-3: delta[(i*nl + (l-lmin))*nsrc + s] = sum_n w_tau[n] S[s][i][n] j_l(k_i (tau0 - tau_n))
- * S is [nsrc][nk][ntau] row-major.  If absdelta is not NULL it receives
- * sum_n |w_tau[n] S[s][i][n] j_l(x)| in the same layout (the scale used for
- * normwise comparisons).
+ * The E-mode radial kernel (Sec. 2.1, Eq. 3 and the text below it):
+ *   eps_l(x) = sqrt((l+2)! / (l-2)!) j_l(x) / x^2 = sqrt((l-1) l (l+1) (l+2)) j_l(x) / x^2,
+ * for l = 0..lmax into out[0..lmax] (0 for l < 2, where the factorial ratio
+ * vanishes).  At x -> 0, j_l(x) / x^2 -> x^(l-2) / (2l+1)!!: 1/15 for l = 2 and
+ * 0 above, used for x < 1e-150 (where x^2 would underflow).  jl is scratch
+ * for j_l (lmax + 1 values, distinct from out).
  */
-int oracle_project(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
-                   const double *k, const double *tau, const double *w_tau, const double *S,
-                   int32_t nsrc, double *delta, double *absdelta)
+/* eps_l(x) from j_l(x), l = 0..lmax (jl and out must not overlap). */
+static void eps_from_jl(int32_t lmax, double x, const double *jl, double *out)
+{
+    for (int32_t l = 0; l <= lmax; ++l)
+        out[l] = 0.0;
+    if (x < 1e-150) {
+        if (lmax >= 2)
+            out[2] = sqrt(24.0) / 15.0;
+        return;
+    }
+    const double ix2 = 1.0 / (x * x);
+    for (int32_t l = 2; l <= lmax; ++l) {
+        const double f = (double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2);
+        out[l] = sqrt(f) * (jl[l] * ix2);
+    }
+}
+
+int oracle_eps_l(int32_t lmax, double x, double *jl, double *out)
+{
+    if (lmax < 0 || !(x >= 0.0) || !isfinite(x) || jl == NULL || out == NULL || jl == out)
+        return OR_ERR_INVALID;
+    int rc = oracle_sph_jl(lmax, x, jl);
+    if (rc != OR_OK)
+        return rc;
+    eps_from_jl(lmax, x, jl, out);
+    return OR_OK;
+}
+
+/*
+ * Eq. 2-3: delta[(i*nl + (l-lmin))*nsrc + s] = sum_n w_tau[n] S[s][i][n] K_s,l(k_i (tau0 - tau_n))
+ * with K_s,l = eps_l for the sources whose bit is set in eps_mask and j_l for
+ * the others.  S is [nsrc][nk][ntau] row-major.  If absdelta is not NULL it
+ * receives sum_n |w_tau[n] S[s][i][n] K_s,l(x)| in the same layout (the scale
+ * used for normwise comparisons).
+ */
+int oracle_project_kernels(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
+                           const double *k, const double *tau, const double *w_tau,
+                           const double *S, int32_t nsrc, uint32_t eps_mask, double *delta,
+                           double *absdelta)
 {
     if (lmin < 0 || lmax < lmin || nk < 0 || ntau < 0 || nsrc < 1 || k == NULL || tau == NULL ||
         w_tau == NULL || S == NULL || delta == NULL)
@@ -186,13 +224,14 @@ int oracle_project(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double 
     {
         flush_subnormals();
         double *jl = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
-        if (jl == NULL) {
+        double *el = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        if (jl == NULL || el == NULL) {
 #pragma omp atomic write
             bad = OR_ERR_OOM;
         }
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < nk; ++i) {
-            if (jl == NULL)
+            if (jl == NULL || el == NULL)
                 continue;
             double *d = delta + i * nl * nsrc;
             double *a = absdelta ? absdelta + i * nl * nsrc : NULL;
@@ -209,12 +248,15 @@ int oracle_project(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double 
                     bad = OR_ERR_INVALID;
                     continue;
                 }
+                if (eps_mask != 0)
+                    eps_from_jl(lmax, x, jl, el);
                 for (int32_t s = 0; s < nsrc; ++s) {
                     double ws = w_tau[n] * S[((int64_t)s * nk + i) * ntau + n];
                     if (ws == 0.0)
                         continue; /* adds exactly zero */
+                    const double *K = ((eps_mask >> s) & 1u) ? el : jl;
                     for (int32_t l = lmin; l <= lmax; ++l) {
-                        double term = ws * jl[l];
+                        double term = ws * K[l];
                         d[(int64_t)(l - lmin) * nsrc + s] += term;
                         if (a)
                             a[(int64_t)(l - lmin) * nsrc + s] += fabs(term);
@@ -223,8 +265,18 @@ int oracle_project(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double 
             }
         }
         free(jl);
+        free(el);
     }
     return bad;
+}
+
+/* Eq. 2-3 with the j_l kernel for every source. */
+int oracle_project(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
+                   const double *k, const double *tau, const double *w_tau, const double *S,
+                   int32_t nsrc, double *delta, double *absdelta)
+{
+    return oracle_project_kernels(lmin, lmax, nk, ntau, tau0, k, tau, w_tau, S, nsrc, 0u, delta,
+                                  absdelta);
 }
 
 /*
