@@ -128,6 +128,26 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
                 int32_t nsrc, int32_t prec, void *delta, void *stream);
 
 /*
+ * LOS projection with a choice of radial kernel per source (Sec. 2.1, Eq. 3
+ * and the text below it): as los_project, except that every source s whose
+ * bit is set in kernel_mask is projected on the E-mode kernel
+ *
+ *   eps_l(x) = sqrt((l+2)! / (l-2)!) j_l(x) / x^2
+ *            = sqrt((l-1) l (l+1) (l+2)) j_l(x) / x^2,
+ *
+ * whose x -> 0 limit is sqrt(24)/15 at l = 2 and 0 above (a node at
+ * tau = tau0 adds w S sqrt(24)/15 to l = 2), and the others on j_l.
+ * los_project is the kernel_mask = 0 case.  Errors: LOS_ERR_INVALID for a
+ * mask bit >= nsrc; LOS_ERR_UNSUPPORTED for a non-zero mask with
+ * prec != LOS_FP64 or with the two-pass FP64 kernel (environment
+ * LOS_PROJ_SCHEME=0).
+ */
+int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
+                        double tau0, const double *k, const double *tau, const double *w_tau,
+                        const void *S, int32_t nsrc, uint32_t kernel_mask, int32_t prec,
+                        void *delta, void *stream);
+
+/*
  * Angular power spectra, Eq. 1 with the ln k quadrature written out:
  *
  *   cl[p * nl + l'] = 4 pi sum_i w_lnk[i] * Pk[i]

@@ -217,9 +217,10 @@ int los_bessel_table(los_ctx *ctx, const double *x, int64_t nx, int32_t lmin, in
   return ok();
 }
 
-int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
-                const double *k, const double *tau, const double *w_tau, const void *S,
-                int32_t nsrc, int32_t prec, void *delta, void *stream) {
+int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
+                        double tau0, const double *k, const double *tau, const double *w_tau,
+                        const void *S, int32_t nsrc, uint32_t kernel_mask, int32_t prec,
+                        void *delta, void *stream) {
   if (!ctx) return fail(LOS_ERR_INVALID, "los_project: ctx is NULL");
   if (lmin < 2 || lmax < lmin || lmax > 16000)
     return fail(LOS_ERR_INVALID, "los_project: need 2 <= lmin <= lmax <= 16000 (got %d, %d)",
@@ -235,14 +236,22 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
     return fail(LOS_ERR_INVALID, "los_project: NULL array");
   if (prec != LOS_FP64 && prec != LOS_FP32 && prec != LOS_BF16X3)
     return fail(LOS_ERR_INVALID, "los_project: unknown precision %d", prec);
-  if (prec != LOS_FP64)
+  if (nsrc < 32 && (kernel_mask >> nsrc) != 0)
+    return fail(LOS_ERR_INVALID, "los_project: kernel mask 0x%x names a source >= nsrc = %d",
+                kernel_mask, nsrc);
+  if (prec != LOS_FP64) {
+    if (kernel_mask != 0)
+      return fail(LOS_ERR_UNSUPPORTED, "los_project: the E-mode kernel is FP64 only");
     return project_mixed(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S, nsrc,
                          prec, (float *)delta, (hipStream_t)stream);
+  }
 
   // Default: the single descending sweep; LOS_PROJ_SCHEME=0 selects the
   // two-pass kernel (ascending upward, then descending Miller).
   const char *scheme = std::getenv("LOS_PROJ_SCHEME");
   const bool desc = !(scheme && std::atoi(scheme) == 0);
+  if (!desc && kernel_mask != 0)
+    return fail(LOS_ERR_UNSUPPORTED, "los_project: the E-mode kernel needs the sweep scheme");
   los::ProjectShape sh =
       desc ? los::project_fp64_desc_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"),
                                           env_int("LOS_PROJ_SLOTS"), env_int("LOS_PROJ_BLOCK"),
@@ -267,10 +276,18 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
   a.w = w_tau;
   a.S = (const double *)S;
   a.delta = (double *)delta;
+  a.emask = kernel_mask;
   hipError_t e = desc ? los::project_fp64_desc_launch(a, nsrc, sh, (hipStream_t)stream)
                       : los::project_fp64_launch(a, nsrc, sh, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "los_project launch");
   return ok();
+}
+
+int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
+                const double *k, const double *tau, const double *w_tau, const void *S,
+                int32_t nsrc, int32_t prec, void *delta, void *stream) {
+  return los_project_kernels(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, S, nsrc, 0u, prec,
+                             delta, stream);
 }
 
 int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc, int32_t nl,

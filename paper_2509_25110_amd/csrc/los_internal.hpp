@@ -18,6 +18,7 @@ struct ProjectArgs {
   const double *k, *tau, *w;
   const double *S;  // [nsrc][nk][ntau]
   double *delta;    // [nk][nl][nsrc]
+  uint32_t emask;   // bit s: source s uses the E-mode kernel eps_l (sweep kernel only)
 };
 
 // Launch shape chosen by the host for the FP64 projection.

@@ -18,6 +18,10 @@
 //     direction above the turning point and neutrally stable below it, so one
 //     sweep covers the whole band with no second pass and no read-modify-write
 //     of delta.
+// E-mode sources (bit s of emask; Sec. 2.1, Eq. 3: eps_l(x) =
+// sqrt((l+2)!/(l-2)!) j_l(x) / x^2): their values are scaled by 1/x^2 per node
+// as they are loaded and their output rows by sqrt((l-1) l (l+1) (l+2)); a node
+// with x below kXTiny adds its limit w S sqrt(24)/15 to l = 2 only.
 #include "bessel_dev.hpp"
 #include "fp64_common.hpp"
 #include "los_internal.hpp"
@@ -186,6 +190,26 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   __syncthreads();
   const int top_blk = bnd[0];
 
+  // E-mode limit at x -> 0: j_2(x)/x^2 -> 1/15 (higher l -> 0)
+  double e2[NSRC];
+#pragma unroll
+  for (int s = 0; s < NSRC; ++s) e2[s] = 0.0;
+  if (a.emask != 0 && lmin == 2) {
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      const int n = (w + W * j) * 64 + lane;
+      if (n < ntau && ixs[n] == 0.0) {
+        const double x = kk * (a.tau0 - a.tau[n]);
+        if (x < kXTiny) {
+          const double wn = a.w[n];
+#pragma unroll
+          for (int s = 0; s < NSRC; ++s)
+            if ((a.emask >> s) & 1u) e2[s] += wn * srow[s][n] * (1.0 / 15.0);
+        }
+      }
+    }
+  }
+
   double *drow = a.delta + ki * (int64_t)a.nl * NSRC;
   // blocks above every lane's top row are zero
   if (w == 0 && lane < NV) {
@@ -195,7 +219,9 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
     }
   }
   int parity = 0;
-  for (int bi = top_blk; bi >= 0; --bi) {
+  // with E-mode limit terms, block 0 is swept even when no node reaches it
+  const int first = (a.emask != 0 && lmin == 2 && top_blk < 0) ? 0 : top_blk;
+  for (int bi = first; bi >= 0; --bi) {
     const int b = lmin + bi * B;
     const int top = b + B - 1;
     const uint64_t fm = slot_mask(thF >= bi);        // all lanes live through the block
@@ -213,7 +239,16 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         int n = nb + lane;
         asm volatile("" : "+v"(n));
         if (j + 1 < T) load_s<NSRC>(svn, srow, n + W * 64, ntau);
-        if (has(fm, j)) sweep_slot<NSRC, B, false>(acc, Jn[j], Jc[j], ixs[n], sv, top, 0);
+        if (has(fm, j)) {
+          const double ix = ixs[n];
+          if (a.emask != 0) {  // uniform
+            const double i2 = ix * ix;
+#pragma unroll
+            for (int s = 0; s < NSRC; ++s)
+              if ((a.emask >> s) & 1u) sv[s] *= i2;
+          }
+          sweep_slot<NSRC, B, false>(acc, Jn[j], Jc[j], ix, sv, top, 0);
+        }
 #pragma unroll
         for (int s = 0; s < NSRC; ++s) sv[s] = svn[s];
       }
@@ -227,15 +262,27 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
       if (has(pm, j)) {
         double sv[NSRC];
         load_s<NSRC>(sv, srow, n, ntau);
+        if (a.emask != 0) {  // uniform
+          const double i2 = ixs[n] * ixs[n];
+#pragma unroll
+          for (int s = 0; s < NSRC; ++s)
+            if ((a.emask >> s) & 1u) sv[s] *= i2;
+        }
         int rel = rs[n] - b;  // rows b .. b + rel are live (rel < 0: none)
         asm volatile("" : "+v"(rel));
         sweep_slot<NSRC, B, true>(acc, Jn[j], Jc[j], ixs[n], sv, top, rel);
       }
     }
-    const double tot = wg_reduce<NV>(acc, stage, cross0 + parity * W * NV, W, w, lane);
+    if (bi == 0) {  // row l = lmin: the x -> 0 E-mode terms (zero unless emask and lmin = 2)
+#pragma unroll
+      for (int s = 0; s < NSRC; ++s) acc[s] += e2[s];
+    }
+    double tot = wg_reduce<NV>(acc, stage, cross0 + parity * W * NV, W, w, lane);
     parity ^= 1;
     if (w == 0 && lane < NV) {
       const int l = b + lane / NSRC;
+      if ((a.emask >> (lane % NSRC)) & 1u)
+        tot *= sqrt((double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2));
       if (l <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] = tot;
     }
   }

@@ -33,7 +33,7 @@ _STATUS = {1: "LOS_ERR_INVALID", 2: "LOS_ERR_HIP", 3: "LOS_ERR_OOM", 4: "LOS_ERR
 
 # every symbol include/los.h declares
 EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
-           "los_bessel_table", "los_project", "cl_integrate", "los_batch_create",
+           "los_bessel_table", "los_project", "los_project_kernels", "cl_integrate", "los_batch_create",
            "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_destroy",
            "emu_create", "emu_destroy", "emu_nparams", "emu_get_params", "emu_set_params",
            "emu_get_pca", "emu_set_pca", "emu_forward", "emu_loss_grad", "emu_fit", "emu_train",
@@ -64,6 +64,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.los_bessel_table.argtypes = [vp, vp, i64, i32, i32, vp, vp]
     lib.los_project.restype = ctypes.c_int
     lib.los_project.argtypes = [vp, i32, i32, i64, i64, dbl, vp, vp, vp, vp, i32, i32, vp, vp]
+    lib.los_project_kernels.restype = ctypes.c_int
+    lib.los_project_kernels.argtypes = [vp, i32, i32, i64, i64, dbl, vp, vp, vp, vp, i32,
+                                        ctypes.c_uint32, i32, vp, vp]
     lib.cl_integrate.restype = ctypes.c_int
     lib.cl_integrate.argtypes = [vp, vp, i32, i32, i32, i64, vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
@@ -189,6 +192,27 @@ class Context:
         _need(delta, S.dtype, nk * nl * nsrc, "delta")
         _check(lib().los_project(self._h, lmin, lmax, nk, ntau, float(tau0), _ptr(k), _ptr(tau),
                                  _ptr(w_tau), _ptr(S), nsrc, prec, _ptr(delta), _stream(stream)))
+        return delta
+
+    def los_project_kernels(self, lmin: int, lmax: int, k: torch.Tensor, tau: torch.Tensor,
+                            tau0: float, w_tau: torch.Tensor, S: torch.Tensor, kernel_mask: int,
+                            prec: int = LOS_FP64, delta: Optional[torch.Tensor] = None,
+                            stream=None) -> torch.Tensor:
+        """los_project with the E-mode kernel eps_l for the sources set in kernel_mask."""
+        nsrc, nk, ntau = S.shape
+        nl = lmax - lmin + 1
+        want = torch.float64 if prec == LOS_FP64 else torch.float32
+        if S.dtype != want:
+            raise ValueError("S must be %s for precision %d (got %s)" % (want, prec, S.dtype))
+        if delta is None:
+            delta = torch.empty((nk, nl, nsrc), dtype=S.dtype, device=S.device)
+        _need(k, torch.float64, nk, "k")
+        _need(tau, torch.float64, ntau, "tau")
+        _need(w_tau, torch.float64, ntau, "w_tau")
+        _need(delta, S.dtype, nk * nl * nsrc, "delta")
+        _check(lib().los_project_kernels(self._h, lmin, lmax, nk, ntau, float(tau0), _ptr(k),
+                                         _ptr(tau), _ptr(w_tau), _ptr(S), nsrc, int(kernel_mask),
+                                         prec, _ptr(delta), _stream(stream)))
         return delta
 
     def cl_integrate(self, delta: torch.Tensor, w_lnk: torch.Tensor, Pk: torch.Tensor,

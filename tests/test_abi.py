@@ -86,6 +86,16 @@ def test_project_argument_validation(lib):
     assert rc == 1 and b"NULL" in lib.los_last_error()
 
 
+def test_project_kernels_validation(lib):
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)
+    # a kernel-mask bit for a source that does not exist
+    assert lib.los_project_kernels(ctx, 2, 10, 4, 8, 1.0, p, p, p, p, 2, 0b100, 0, p, None) == 1
+    assert b"mask" in lib.los_last_error()
+    # the E-mode kernel is FP64 only
+    assert lib.los_project_kernels(ctx, 2, 10, 4, 8, 1.0, p, p, p, p, 2, 0b10, 2, p, None) == 4
+
+
 def test_cl_and_table_validation(lib):
     ctx, _keep = _dummy_ctx()
     p = ctypes.c_void_p(16)
