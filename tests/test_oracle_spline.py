@@ -1,0 +1,109 @@
+"""Pins of the source-interpolation oracle (natural cubic spline in k at each tau
+node; the reading of the InterpolateSources step of the gCAMB paper, Sec. 3.2)
+against results fixed independently of it: a brute-force piecewise-cubic solve
+in the power basis, scipy's natural CubicSpline, straight lines (reproduced
+exactly) and the interpolation / end conditions."""
+import numpy as np
+import pytest
+from scipy.interpolate import CubicSpline
+
+from oracle import spline_oracle as so
+
+
+def brute_force_spline(q, y):
+    """Coefficients c[j] of s(k) = c0 + c1 t + c2 t^2 + c3 t^3, t = k - q_j, from the full
+    system: interpolation at both ends of every interval, C1 and C2 continuity at
+    interior knots, s'' = 0 at both ends."""
+    N = q.size
+    m = N - 1
+    A = np.zeros((4 * m, 4 * m))
+    b = np.zeros(4 * m)
+    r = 0
+    for j in range(m):
+        h = q[j + 1] - q[j]
+        A[r, 4 * j] = 1.0; b[r] = y[j]; r += 1
+        A[r, 4 * j:4 * j + 4] = [1.0, h, h * h, h ** 3]; b[r] = y[j + 1]; r += 1
+        if j + 1 < m:
+            A[r, 4 * j:4 * j + 4] = [0.0, 1.0, 2 * h, 3 * h * h]; A[r, 4 * j + 5] = -1.0; r += 1
+            A[r, 4 * j:4 * j + 4] = [0.0, 0.0, 2.0, 6 * h]; A[r, 4 * j + 6] = -2.0; r += 1
+    A[r, 2] = 2.0; r += 1
+    h = q[-1] - q[-2]
+    A[r, 4 * (m - 1):4 * m] = [0.0, 0.0, 2.0, 6 * h]; r += 1
+    assert r == 4 * m
+    return np.linalg.solve(A, b).reshape(m, 4)
+
+
+def brute_eval(q, c, k):
+    j = np.clip(np.searchsorted(q, k, side="right") - 1, 0, q.size - 2)
+    t = k - q[j]
+    return c[j, 0] + t * (c[j, 1] + t * (c[j, 2] + t * c[j, 3]))
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 7, 25])
+def test_vs_brute_force_power_basis(N):
+    rng = np.random.default_rng(100 + N)
+    q = np.cumsum(rng.uniform(0.2, 2.0, N))
+    y = rng.normal(size=(2, N, 3))
+    k = np.concatenate([np.linspace(q[0] - 0.5, q[-1] + 0.5, 301), q])
+    got = so.interpolate(q, y, k)
+    M = so.second_derivatives(q, y)
+    for s in range(2):
+        for n in range(3):
+            c = brute_force_spline(q, y[s, :, n])
+            ref = brute_eval(q, c, k)
+            scale = np.abs(y[s, :, n]).max()
+            np.testing.assert_allclose(got[s, :, n], ref, rtol=0, atol=1e-12 * scale)
+            # M_j = s''(q_j) = 2 c2 of the interval starting at q_j (and 0 at the last knot)
+            np.testing.assert_allclose(M[s, :-1, n], 2 * c[:, 2], rtol=0,
+                                       atol=1e-11 * scale / np.diff(q).min() ** 2)
+            assert M[s, 0, n] == 0.0 and M[s, -1, n] == 0.0
+
+
+def test_vs_scipy_natural_cubic_spline():
+    rng = np.random.default_rng(7)
+    q = np.exp(np.linspace(np.log(1e-4), np.log(0.5), 200))
+    Sc = rng.normal(size=(3, q.size, 5))
+    k = np.exp(np.linspace(np.log(1e-4), np.log(0.5), 777))
+    got = so.interpolate(q, Sc, k)
+    M = so.second_derivatives(q, Sc)
+    for s in range(3):
+        for n in range(5):
+            cs = CubicSpline(q, Sc[s, :, n], bc_type="natural")
+            np.testing.assert_allclose(got[s, :, n], cs(k), rtol=0, atol=1e-11)
+            np.testing.assert_allclose(M[s, :, n], cs(q, 2), rtol=1e-9,
+                                       atol=1e-9 * np.abs(cs(q, 2)).max())
+
+
+def test_straight_lines_exact_and_knots():
+    q = np.array([0.1, 0.15, 0.4, 0.41, 0.9, 1.3])
+    Sc = np.empty((1, q.size, 2))
+    Sc[0, :, 0] = 3.0 * q - 1.0
+    Sc[0, :, 1] = -0.5 * q + 2.0
+    M = so.second_derivatives(q, Sc)
+    assert np.abs(M).max() < 1e-12
+    k = np.linspace(0.0, 1.5, 41)
+    got = so.evaluate(q, Sc, M, k)
+    np.testing.assert_allclose(got[0, :, 0], 3.0 * k - 1.0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(got[0, :, 1], -0.5 * k + 2.0, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(3)
+    Y = rng.normal(size=(2, q.size, 4))
+    np.testing.assert_allclose(so.interpolate(q, Y, q), Y, rtol=0, atol=1e-14)
+
+
+def test_convergence_interior():
+    """For f = sin, the interior error of the natural spline falls as h^4 (away from the
+    ends, where the zero-curvature condition costs O(h^2))."""
+    errs = []
+    for N in (41, 81, 161):
+        q = np.linspace(0.0, 4.0, N)
+        Sc = np.sin(q)[None, :, None]
+        k = np.linspace(1.5, 2.5, 101)
+        errs.append(np.abs(so.interpolate(q, Sc, k)[0, :, 0] - np.sin(k)).max())
+    assert errs[1] < errs[0] / 12 and errs[2] < errs[1] / 12
+
+
+def test_rejects_bad_grids():
+    with pytest.raises(ValueError):
+        so.second_derivatives(np.array([0.0, 1.0, 1.0]), np.zeros((1, 3, 1)))
+    with pytest.raises(ValueError):
+        so.second_derivatives(np.array([0.0]), np.zeros((1, 1, 1)))
