@@ -10,6 +10,11 @@ with all inputs resident in HBM.  Prints ONE JSON line.
 
 --config C3 --prec bf16x3 (or fp32) runs the mixed-precision workload (l up to
 5000, 8000 k, 4000 tau; S and Delta in FP32, j_l in FP64, C_l sum in FP64).
+
+--interp gives the sources on a coarse k grid (1000 knots for C2, 2000 for C3)
+and adds the source preparation to every step: los_spline_sources +
+los_interp_sources (natural cubic spline in k onto the workload's k grid),
+then the projection and C_l as above.
 """
 import argparse
 import json
@@ -225,6 +230,8 @@ def run_batch(args):
         "tile": [info["tile_mb"], info["tile_nc"]], "chunks": info["chunks"],
         "max_rel_err_vs_oracle": err,
     }
+    if interp is not None:
+        out["interp"] = interp
     if not args.no_cpu_baseline:
         import oracle
         m = 3
@@ -429,6 +436,8 @@ def main():
     ap.add_argument("--emu-epochs", type=int, default=300, help="C5: training epochs")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="C4: also time the FP64 plain path on a sample of the batch's models")
+    ap.add_argument("--interp", action="store_true",
+                    help="C1-C3: sources on the coarse k grid, splined onto the LOS grid each step")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -467,7 +476,18 @@ def main():
     ctx = los.Context()
     stream = torch.cuda.current_stream()
 
+    if args.interp:
+        cs = inputs.coarse_sources(wl, inputs.COARSE_NK[wl.name])
+        q, Sc = dv(cs.q), dv(cs.Sc)
+        M = torch.empty_like(Sc)
+
+    def prepare():
+        if args.interp:
+            ctx.los_spline_sources(q, Sc, M=M)
+            ctx.los_interp_sources(q, Sc, M, k, out_prec=0 if prec == 0 else 1, S=S)
+
     def step():
+        prepare()
         ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
         ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
 
@@ -483,11 +503,14 @@ def main():
     K = args.steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(K)]
+    evi = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record(stream)
     for i in range(K):
+        evi[i].record(stream)
+        prepare()
         ev[i][0].record(stream)
         ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
         ev[i][1].record(stream)
@@ -497,6 +520,7 @@ def main():
     wall = time.perf_counter() - wall0
     total_ms = start.elapsed_time(end)
     proj_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    prep_ms = float(np.mean([a.elapsed_time(b[0]) for a, b in zip(evi, ev)]))
     ms_per_step = total_ms / K
 
     tp, band = tp_and_band_counts(wl)
@@ -504,6 +528,17 @@ def main():
     achieved = flops / (proj_ms * 1e-3) / 1e12
     gfma = wl.nsrc * tp / (ms_per_step * 1e-3) / 1e9
     err = golden_error(cl.cpu().numpy(), wl)
+    interp = None
+    if args.interp:
+        nkc = cs.q.size
+        # algorithmic bytes: the spline reads Sc and writes M; the evaluation reads Sc and M
+        # once and writes S
+        byts = 8.0 * wl.nsrc * wl.ntau * (2 * nkc + 2 * nkc) + S.element_size() * S.numel()
+        interp = {"nkc": int(nkc), "ms": prep_ms, "bytes": byts,
+                  "GB_per_s": byts / (prep_ms * 1e-3) / 1e9,
+                  "frac_hbm": byts / (prep_ms * 1e-3) / 8e12,
+                  "cl_rel_dev_vs_direct_sources": err}
+        err = None  # the golden C_l are for sources given on the LOS grid itself
 
     path = {0: "FP64 plain path", 1: "FP32 MFMA path", 2: "split-BF16x3 MFMA path"}[prec]
     kernel = fp64_kernel()[0] if prec == 0 else "jtable_kernel + mfma_gemm_kernel"
@@ -520,7 +555,9 @@ def main():
         "vs_baseline": None,
         "dtype": {0: "f64", 1: "f64 j_l, f32 product", 2: "f64 j_l, bf16x3 product"}[prec],
         "data": "synthetic",
-        "config": {"workload": "%s: %s, %s" % (wl.name, inputs.DESCRIPTIONS[wl.name], path),
+        "config": {"workload": "%s: %s, %s%s" % (wl.name, inputs.DESCRIPTIONS[wl.name], path,
+                                                 ", sources splined from %d coarse k each step"
+                                                 % inputs.COARSE_NK[wl.name] if args.interp else ""),
                    "nk": wl.nk, "ntau": wl.ntau, "lmax": wl.lmax, "nsrc": wl.nsrc,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
@@ -532,11 +569,13 @@ def main():
         "tp_entries": tp,
         "band_entries": band,
         "first_call_ms": first_ms,
-        "cl_ms": ms_per_step - proj_ms,
+        "cl_ms": ms_per_step - proj_ms - prep_ms,
         "wall_s_timed": wall,
         "max_rel_err_vs_oracle": err,
     }
-    if not args.no_cpu_baseline and rank == 0:
+    if interp is not None:
+        out["interp"] = interp
+    if not args.no_cpu_baseline and rank == 0 and not args.interp:
         stride = args.cpu_stride or {"C3": 4}.get(wl.name, 1)
         out["cpu_baseline"] = cpu_baseline(wl, stride)
     ctx.close()

@@ -165,6 +165,45 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
                  int32_t npairs, double *cl, void *stream);
 
 /*
+ * Source preparation (Sec. 3.2: before the integrals, InterpolateSources
+ * brings the source data onto the integration grid; the paper names the step
+ * but not its scheme).  Here the sources are given on a coarse wavenumber
+ * grid q_0 < ... < q_{nkc-1} at the projection's tau nodes, and each
+ * (source, tau node) column is carried to the projection's k grid by the
+ * natural cubic spline in k through its nkc values:
+ *
+ *   on [q_j, q_{j+1}], h = q_{j+1} - q_j, A = (q_{j+1} - k)/h, B = (k - q_j)/h:
+ *   s(k) = A y_j + B y_{j+1} + ((A^3 - A) M_j + (B^3 - B) M_{j+1}) h^2 / 6,
+ *
+ * M the second derivatives (continuous s'' at the knots, M_0 = M_{nkc-1} = 0).
+ *
+ * los_spline_sources: M[(s * nkc + j) * ntau + n] for the columns of
+ *   Sc[(s * nkc + j) * ntau + n] (s < nsrc, j < nkc, n < ntau).  q: device,
+ *   nkc doubles, strictly increasing (not checked: other grids give undefined
+ *   values, never an access out of bounds).  Sc, M: device, nsrc*nkc*ntau
+ *   doubles, M distinct from Sc.  1 <= nsrc <= 64, 2 <= nkc <= 16386,
+ *   ntau >= 1, nsrc*ntau < 2^31.  The tridiagonal systems are solved in FP64
+ *   (segments of 16 rows plus a reduced system for the segment ends; no
+ *   pivoting is needed, the matrix being strictly diagonally dominant).
+ *   Uses the context's workspace (about 40 doubles per 16 knots).
+ *
+ * los_interp_sources: S[(s * nk + i) * ntau + n] = s(k[i]) for the same
+ *   columns, with M from los_spline_sources.  k: device, nk doubles; a k
+ *   outside [q_0, q_{nkc-1}] takes the cubic of the end interval.  S: device,
+ *   nsrc*nk*ntau values, double for out_prec == LOS_FP64, float (the FP64
+ *   value rounded) for LOS_FP32; distinct from Sc and M.  The result is the
+ *   S layout that los_project takes.  nk == 0 is a no-op.
+ *
+ * Errors: LOS_ERR_INVALID for NULL pointers, aliasing, out-of-range sizes or
+ * an unknown out_prec.
+ */
+int los_spline_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, const double *q,
+                       const double *Sc, double *M, void *stream);
+int los_interp_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, const double *q,
+                       const double *Sc, const double *M, int64_t nk, const double *k,
+                       int32_t out_prec, void *S, void *stream);
+
+/*
  * Batched solve (Sec. 3.2 / Algorithm 1: the projection is independent per k;
  * Eq. 2-3 and Eq. 1 per model).  nmodels models share one master k grid and
  * one tau grid; model m uses master rows k_index[koff[m] .. koff[m+1]-1]

@@ -16,7 +16,7 @@
 // Workspace slots of a context: the C_l partial sums and the Bessel tables
 // of the MFMA projection live in separate buffers, so a C_l call queued
 // behind a projection never reallocates memory the projection still reads.
-enum { WS_CL = 0, WS_JTAB = 1, WS_COUNT = 2 };
+enum { WS_CL = 0, WS_JTAB = 1, WS_SPLINE = 2, WS_COUNT = 3 };
 
 struct los_ctx {
   int device = 0;
@@ -328,6 +328,64 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
   a.partial = (double *)ws;
   hipError_t e = los::cl_launch(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "cl_integrate launch");
+  return ok();
+}
+
+namespace {
+
+int spline_check(const char *fn, int32_t nsrc, int64_t nkc, int64_t ntau, const double *q,
+                 const double *Sc) {
+  if (nsrc < 1 || nsrc > 64) return fail(LOS_ERR_INVALID, "%s: nsrc = %d out of [1, 64]", fn, nsrc);
+  const int64_t nmax = 2 + 16 * los::kSplineMaxSegments;
+  if (nkc < 2 || nkc > nmax)
+    return fail(LOS_ERR_INVALID, "%s: nkc = %lld out of [2, %lld]", fn, (long long)nkc,
+                (long long)nmax);
+  if (ntau < 1 || ntau > ((int64_t)1 << 31) - 1 || (int64_t)nsrc * ntau > ((int64_t)1 << 31) - 1)
+    return fail(LOS_ERR_INVALID, "%s: ntau = %lld out of range", fn, (long long)ntau);
+  if (!q || !Sc) return fail(LOS_ERR_INVALID, "%s: NULL array", fn);
+  return LOS_OK;
+}
+
+}  // namespace
+
+int los_spline_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, const double *q,
+                       const double *Sc, double *M, void *stream) {
+  if (!ctx) return fail(LOS_ERR_INVALID, "los_spline_sources: ctx is NULL");
+  int rc = spline_check("los_spline_sources", nsrc, nkc, ntau, q, Sc);
+  if (rc != LOS_OK) return rc;
+  if (!M) return fail(LOS_ERR_INVALID, "los_spline_sources: NULL array");
+  if ((const double *)M == Sc)
+    return fail(LOS_ERR_INVALID, "los_spline_sources: M must not alias Sc");
+  los::SplineTabs t{};
+  if (los::spline_segments(nkc) > 0) {
+    void *ws = nullptr;
+    rc = ws_reserve(ctx, WS_SPLINE, sizeof(double) * los::spline_tab_doubles(nkc), &ws);
+    if (rc != LOS_OK) return rc;
+    t = los::spline_tabs_at((double *)ws, nkc);
+  }
+  hipError_t e = los::spline_solve_launch(q, Sc, M, nkc, (int64_t)nsrc * ntau, ntau, t,
+                                          (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "los_spline_sources launch");
+  return ok();
+}
+
+int los_interp_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, const double *q,
+                       const double *Sc, const double *M, int64_t nk, const double *k,
+                       int32_t out_prec, void *S, void *stream) {
+  if (!ctx) return fail(LOS_ERR_INVALID, "los_interp_sources: ctx is NULL");
+  int rc = spline_check("los_interp_sources", nsrc, nkc, ntau, q, Sc);
+  if (rc != LOS_OK) return rc;
+  if (nk < 0 || nk > ((int64_t)1 << 31) - 1)
+    return fail(LOS_ERR_INVALID, "los_interp_sources: nk = %lld out of range", (long long)nk);
+  if (out_prec != LOS_FP64 && out_prec != LOS_FP32)
+    return fail(LOS_ERR_INVALID, "los_interp_sources: out_prec must be LOS_FP64 or LOS_FP32");
+  if (nk == 0) return ok();
+  if (!M || !k || !S) return fail(LOS_ERR_INVALID, "los_interp_sources: NULL array");
+  if ((const void *)S == (const void *)Sc || (const void *)S == (const void *)M)
+    return fail(LOS_ERR_INVALID, "los_interp_sources: S must not alias Sc or M");
+  hipError_t e = los::spline_eval_launch(q, nkc, Sc, M, k, nk, nsrc, ntau, out_prec, S,
+                                         (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "los_interp_sources launch");
   return ok();
 }
 

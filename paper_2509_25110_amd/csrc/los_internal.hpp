@@ -138,4 +138,25 @@ struct ClArgs {
 int cl_segments(int64_t nk, int nl);
 hipError_t cl_launch(const ClArgs &a, hipStream_t s);
 
+// Natural cubic spline of the sources in k (spline.hip).  The tables depend
+// on the knots only: per interior row (P * 16 rows, padded) the local Thomas
+// factors and the two spikes, per knot interval 1/h, per segment the factors
+// of the 2x2-block reduced system.
+struct SplineTabs {
+  double *sub, *iden, *cp, *v, *w;  // [P * 16]
+  double *ih;                       // [N - 1]
+  double *red;                      // [P][6]
+};
+constexpr int64_t kSplineMaxSegments = 1024;  // N <= 2 + 16 * 1024
+int64_t spline_segments(int64_t N);
+size_t spline_tab_doubles(int64_t N);
+SplineTabs spline_tabs_at(double *ws, int64_t N);
+// M[s][j][n] for the ncols = nsrc * ntau columns of Sc[s][j][n] on knots q[N].
+hipError_t spline_solve_launch(const double *q, const double *Sc, double *M, int64_t N,
+                               int64_t ncols, int64_t ntau, const SplineTabs &t, hipStream_t s);
+// out[s][i][n] = the spline at k[i] (double or float by out_prec).
+hipError_t spline_eval_launch(const double *q, int64_t N, const double *Sc, const double *M,
+                              const double *k, int64_t nk, int nsrc, int64_t ntau, int out_prec,
+                              void *out, hipStream_t s);
+
 }  // namespace los

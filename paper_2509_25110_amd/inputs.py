@@ -147,6 +147,25 @@ def config(name: str) -> Workload:
     return _make(name, **c)
 
 
+# Sources on a coarse wavenumber grid (the grid the perturbation equations are
+# evolved on), to be interpolated in k onto the workload's own k grid: nkc
+# log-spaced knots spanning the same [kmin, kmax].
+COARSE_NK = {"C1": 100, "C2": 1000, "C3": 2000}
+
+
+@dataclasses.dataclass
+class CoarseSources:
+    q: np.ndarray    # [nkc] knots, strictly increasing, q[0] = k[0], q[-1] = k[-1]
+    Sc: np.ndarray   # [nsrc, nkc, ntau] float64, the synthetic sources at the knots
+
+
+def coarse_sources(wl: Workload, nkc: int) -> CoarseSources:
+    """The workload's synthetic sources evaluated on nkc log-spaced knots over its k range."""
+    q = log_k_grid(nkc, float(wl.k[0]), float(wl.k[-1]))
+    kw = {key: wl.params[key] for key in ("tau_star", "width", "a_isw") if key in wl.params}
+    return CoarseSources(q=q, Sc=sources(q, wl.tau, wl.nsrc, **kw))
+
+
 def small(lmax=40, nk=24, kmax=0.02, ntau=200, nsrc=3, kmin=1e-4, **kw) -> Workload:
     """A small workload of the same structure (for quick parity tests)."""
     return _make("small", lmax=lmax, nk=nk, kmax=kmax, ntau=ntau, nsrc=nsrc, kmin=kmin, **kw)

@@ -33,7 +33,8 @@ _STATUS = {1: "LOS_ERR_INVALID", 2: "LOS_ERR_HIP", 3: "LOS_ERR_OOM", 4: "LOS_ERR
 
 # every symbol include/los.h declares
 EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
-           "los_bessel_table", "los_project", "los_project_kernels", "cl_integrate", "los_batch_create",
+           "los_bessel_table", "los_project", "los_project_kernels", "cl_integrate",
+           "los_spline_sources", "los_interp_sources", "los_batch_create",
            "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_destroy",
            "emu_create", "emu_destroy", "emu_nparams", "emu_get_params", "emu_set_params",
            "emu_get_pca", "emu_set_pca", "emu_forward", "emu_loss_grad", "emu_fit", "emu_train",
@@ -70,6 +71,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cl_integrate.restype = ctypes.c_int
     lib.cl_integrate.argtypes = [vp, vp, i32, i32, i32, i64, vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
+    lib.los_spline_sources.restype = ctypes.c_int
+    lib.los_spline_sources.argtypes = [vp, i32, i64, i64, vp, vp, vp, vp]
+    lib.los_interp_sources.restype = ctypes.c_int
+    lib.los_interp_sources.argtypes = [vp, i32, i64, i64, vp, vp, vp, i64, vp, i32, vp, vp]
     lib.los_batch_create.restype = ctypes.c_int
     lib.los_batch_create.argtypes = [vp, i32, i32, vp, vp, vp, i64, i64, vp, i32, i32,
                                      ctypes.POINTER(vp)]
@@ -232,6 +237,37 @@ class Context:
                                   arr, npairs, _ptr(cl), _stream(stream)))
         return cl
 
+
+    def los_spline_sources(self, q: torch.Tensor, Sc: torch.Tensor,
+                           M: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Natural-spline second derivatives in k of Sc[nsrc, nkc, ntau] on the knots q."""
+        nsrc, nkc, ntau = Sc.shape
+        if M is None:
+            M = torch.empty_like(Sc)
+        _need(q, torch.float64, nkc, "q")
+        _need(Sc, torch.float64, nsrc * nkc * ntau, "Sc")
+        _need(M, torch.float64, nsrc * nkc * ntau, "M")
+        _check(lib().los_spline_sources(self._h, nsrc, nkc, ntau, _ptr(q), _ptr(Sc), _ptr(M),
+                                        _stream(stream)))
+        return M
+
+    def los_interp_sources(self, q: torch.Tensor, Sc: torch.Tensor, M: torch.Tensor,
+                           k: torch.Tensor, out_prec: int = LOS_FP64,
+                           S: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """S[nsrc, nk, ntau]: the spline through Sc (second derivatives M) at k."""
+        nsrc, nkc, ntau = Sc.shape
+        nk = k.numel()
+        dt = torch.float64 if out_prec == LOS_FP64 else torch.float32
+        if S is None:
+            S = torch.empty((nsrc, nk, ntau), dtype=dt, device=Sc.device)
+        _need(q, torch.float64, nkc, "q")
+        _need(Sc, torch.float64, nsrc * nkc * ntau, "Sc")
+        _need(M, torch.float64, nsrc * nkc * ntau, "M")
+        _need(k, torch.float64, nk, "k")
+        _need(S, dt, nsrc * nk * ntau, "S")
+        _check(lib().los_interp_sources(self._h, nsrc, nkc, ntau, _ptr(q), _ptr(Sc), _ptr(M), nk,
+                                        _ptr(k), out_prec, _ptr(S), _stream(stream)))
+        return S
 
     def los_batch_create(self, lmax, koff, k_index, nk_master: int, ntau: int,
                          pairs: Sequence[Tuple[int, int]], prec: int = LOS_BF16X3,

@@ -108,3 +108,24 @@ def test_cl_and_table_validation(lib):
     assert lib.los_bessel_table(ctx, p, 5, 4, 3, p, None) == 1                   # lmax < lmin
     assert lib.los_bessel_table(ctx, p, -1, 0, 3, p, None) == 1                  # nx < 0
     assert lib.los_bessel_table(ctx, None, 0, 0, 3, None, None) == 0             # nx == 0: no-op
+
+
+def test_spline_validation(lib):
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)
+    m = ctypes.c_void_p(32)
+    sp, ip = lib.los_spline_sources, lib.los_interp_sources
+    assert sp(ctx, 1, 1, 8, p, p, m, None) == 1           # nkc < 2
+    assert sp(ctx, 1, 2 + 16 * 1024 + 1, 8, p, p, m, None) == 1  # nkc too large
+    assert sp(ctx, 0, 10, 8, p, p, m, None) == 1          # nsrc = 0
+    assert sp(ctx, 65, 10, 8, p, p, m, None) == 1         # nsrc > 64
+    assert sp(ctx, 1, 10, 0, p, p, m, None) == 1          # ntau = 0
+    assert sp(ctx, 1, 10, 8, p, p, p, None) == 1          # M aliases Sc
+    assert b"alias" in lib.los_last_error()
+    assert sp(ctx, 1, 10, 8, None, p, m, None) == 1       # NULL q
+    s = ctypes.c_void_p(48)
+    assert ip(ctx, 1, 10, 8, p, p, m, 4, p, 7, s, None) == 1   # bad out_prec
+    assert ip(ctx, 1, 10, 8, p, p, m, -1, p, 0, s, None) == 1  # nk < 0
+    assert ip(ctx, 1, 10, 8, p, p, m, 4, p, 0, m, None) == 1   # S aliases M
+    assert ip(ctx, 1, 10, 8, p, p, m, 0, None, 0, None, None) == 0  # nk == 0: no-op
+    assert sp(None, 1, 10, 8, p, p, m, None) == 1
