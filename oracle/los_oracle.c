@@ -47,13 +47,29 @@
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
 
-/* Subnormal results (|v| < 2.2e-308) are flushed to zero in every oracle
- * thread: they cannot move any comparison made at the tolerances used, and
- * x86 subnormal arithmetic is ~100x slower.  Everything else is plain IEEE. */
-static void flush_subnormals(void)
+/* Subnormal results (|v| < 2.2e-308) are flushed to zero while oracle code
+ * runs (FTZ and DAZ in the MXCSR of every thread that runs it): they cannot
+ * move any comparison made at the tolerances used, and x86 subnormal
+ * arithmetic is ~100x slower.  Everything else is plain IEEE.  Each entry
+ * point restores the caller's mode on return, so code that runs after it in
+ * the same thread (numpy, the other oracles) keeps IEEE subnormals. */
+static unsigned fp_enter(void)
 {
 #if defined(__SSE2__)
-    _mm_setcsr(_mm_getcsr() | 0x8040); /* FTZ | DAZ */
+    const unsigned saved = _mm_getcsr();
+    _mm_setcsr(saved | 0x8040); /* FTZ | DAZ */
+    return saved;
+#else
+    return 0u;
+#endif
+}
+
+static void fp_leave(unsigned saved)
+{
+#if defined(__SSE2__)
+    _mm_setcsr(saved);
+#else
+    (void)saved;
 #endif
 }
 
@@ -107,10 +123,9 @@ static void jl_miller(int32_t lmax, double x, double *out, int *ex)
         out[l] = ldexp(out[l], ex[l] - e_tot) / norm;
 }
 
-/* j_l(x) for l = 0..lmax, x >= 0, into out[0..lmax]. */
-int oracle_sph_jl(int32_t lmax, double x, double *out)
+/* j_l(x) for l = 0..lmax, x >= 0, into out[0..lmax] (in the oracle's FP mode). */
+static int sph_jl_body(int32_t lmax, double x, double *out)
 {
-    flush_subnormals();
     if (lmax < 0 || !(x >= 0.0) || !isfinite(x) || out == NULL)
         return OR_ERR_INVALID;
     if (x < 1e-150) {
@@ -136,6 +151,14 @@ int oracle_sph_jl(int32_t lmax, double x, double *out)
     return OR_OK;
 }
 
+int oracle_sph_jl(int32_t lmax, double x, double *out)
+{
+    const unsigned fpm = fp_enter();
+    const int rc = sph_jl_body(lmax, x, out);
+    fp_leave(fpm);
+    return rc;
+}
+
 /* Table form: out[(l - lmin) * nx + i] = j_l(x[i]), l = lmin..lmax. */
 int oracle_bessel_table(const double *x, int64_t nx, int32_t lmin, int32_t lmax, double *out)
 {
@@ -144,7 +167,7 @@ int oracle_bessel_table(const double *x, int64_t nx, int32_t lmin, int32_t lmax,
     int bad = 0;
 #pragma omp parallel
     {
-        flush_subnormals();
+        const unsigned fpm = fp_enter();
         double *jl = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
         if (jl == NULL) {
 #pragma omp atomic write
@@ -154,7 +177,7 @@ int oracle_bessel_table(const double *x, int64_t nx, int32_t lmin, int32_t lmax,
         for (int64_t i = 0; i < nx; ++i) {
             if (jl == NULL)
                 continue;
-            if (oracle_sph_jl(lmax, x[i], jl) != OR_OK) {
+            if (sph_jl_body(lmax, x[i], jl) != OR_OK) {
 #pragma omp atomic write
                 bad = OR_ERR_INVALID;
                 continue;
@@ -163,6 +186,7 @@ int oracle_bessel_table(const double *x, int64_t nx, int32_t lmin, int32_t lmax,
                 out[(int64_t)(l - lmin) * nx + i] = jl[l];
         }
         free(jl);
+        fp_leave(fpm);
     }
     return bad;
 }
@@ -196,11 +220,12 @@ int oracle_eps_l(int32_t lmax, double x, double *jl, double *out)
 {
     if (lmax < 0 || !(x >= 0.0) || !isfinite(x) || jl == NULL || out == NULL || jl == out)
         return OR_ERR_INVALID;
-    int rc = oracle_sph_jl(lmax, x, jl);
-    if (rc != OR_OK)
-        return rc;
-    eps_from_jl(lmax, x, jl, out);
-    return OR_OK;
+    const unsigned fpm = fp_enter();
+    int rc = sph_jl_body(lmax, x, jl);
+    if (rc == OR_OK)
+        eps_from_jl(lmax, x, jl, out);
+    fp_leave(fpm);
+    return rc;
 }
 
 /*
@@ -222,7 +247,7 @@ int oracle_project_kernels(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
     int bad = 0;
 #pragma omp parallel
     {
-        flush_subnormals();
+        const unsigned fpm = fp_enter();
         double *jl = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
         double *el = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
         if (jl == NULL || el == NULL) {
@@ -243,7 +268,7 @@ int oracle_project_kernels(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
             for (int64_t n = 0; n < ntau; ++n) {
                 double chi = tau0 - tau[n];
                 double x = k[i] * chi;
-                if (oracle_sph_jl(lmax, x, jl) != OR_OK) {
+                if (sph_jl_body(lmax, x, jl) != OR_OK) {
 #pragma omp atomic write
                     bad = OR_ERR_INVALID;
                     continue;
@@ -266,6 +291,7 @@ int oracle_project_kernels(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
         }
         free(jl);
         free(el);
+        fp_leave(fpm);
     }
     return bad;
 }
@@ -295,18 +321,21 @@ int oracle_cl(int32_t nl, int64_t nk, int32_t nsrc, const double *delta, const d
             pairs[2 * p + 1] >= nsrc)
             return OR_ERR_INVALID;
 #pragma omp parallel
-    flush_subnormals();
-#pragma omp parallel for schedule(static) collapse(2)
-    for (int32_t p = 0; p < npairs; ++p) {
-        for (int32_t l = 0; l < nl; ++l) {
-            int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
-            double acc = 0.0;
-            for (int64_t i = 0; i < nk; ++i) {
-                const double *d = delta + ((int64_t)i * nl + l) * nsrc;
-                acc += w_lnk[i] * Pk[i] * d[a] * d[b];
+    {
+        const unsigned fpm = fp_enter();
+#pragma omp for schedule(static) collapse(2)
+        for (int32_t p = 0; p < npairs; ++p) {
+            for (int32_t l = 0; l < nl; ++l) {
+                int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
+                double acc = 0.0;
+                for (int64_t i = 0; i < nk; ++i) {
+                    const double *d = delta + ((int64_t)i * nl + l) * nsrc;
+                    acc += w_lnk[i] * Pk[i] * d[a] * d[b];
+                }
+                cl[(int64_t)p * nl + l] = 4.0 * OR_PI * acc;
             }
-            cl[(int64_t)p * nl + l] = 4.0 * OR_PI * acc;
         }
+        fp_leave(fpm);
     }
     return OR_OK;
 }

@@ -172,3 +172,22 @@ def test_cl_invariants():
     assert np.all(c[2] ** 2 <= c[0] * c[1] * (1 + 1e-12))            # Cauchy-Schwarz
     c2 = oracle.cl(d, w.w_lnk, 3.0 * w.Pk, pairs)                   # C proportional to A_s
     np.testing.assert_allclose(c2, 3.0 * c, rtol=1e-14)
+
+
+def test_oracle_leaves_caller_fp_mode_alone():
+    """The oracle flushes subnormals only while its own code runs: afterwards numpy in
+    the calling thread still computes with IEEE subnormals (a flushed mode leaking out
+    would change the results of every numpy-based oracle called later)."""
+    import numpy as np
+    import oracle
+    tiny = np.array([1e-310, 3e-320])
+    before = tiny * np.array([1.0, 7.0])
+    oracle.sph_jl(10, 3.0)
+    oracle.eps_l(10, 3.0)
+    oracle.bessel_table(np.array([0.5, 20.0]), 0, 5)
+    d = oracle.project(2, 6, np.array([1e-3]), np.array([0.0, 7000.0]), 14000.0,
+                       np.array([1.0, 1.0]), np.ones((1, 1, 2)))
+    oracle.cl(d, np.array([1.0]), np.array([1.0]), [(0, 0)])
+    after = tiny * np.array([1.0, 7.0])
+    assert np.all(after == before) and np.all(after > 0)
+    assert np.float64(5e-324) > 0 and np.float64(1e-310) / 2 > 0
