@@ -35,9 +35,14 @@ __device__ inline double swap_add16(double a, double b) {
 #endif
 }
 
+// Doubles of one wave's staging area for wg_reduce<NV>: 16 columns of NV + 1
+// (the pad makes both the column writes and the lane-consecutive reads free
+// of LDS bank conflicts).
+constexpr int stage_doubles(int NV) { return 16 * (NV + 1); }
+
 // Reduce v[NV] over the workgroup's lanes.  On return, lane L < NV of wave 0
 // holds the total of index L (other lanes: unspecified).  `stage` is this
-// wave's [NV][16] LDS area, `cross` the [W][NV] area of the current parity.
+// wave's [16][NV + 1] LDS area, `cross` the [W][NV] area of the current parity.
 template <int NV>
 __device__ inline double wg_reduce(double (&v)[NV], double *stage, double *cross, int W, int w,
                                    int lane, bool wave_active = true) {
@@ -60,12 +65,12 @@ __device__ inline double wg_reduce(double (&v)[NV], double *stage, double *cross
   // lane (r, c) now holds, for index p + r*NV/4, the sum over the 4 lanes of column c
   const int r = lane >> 4, c = lane & 15;
 #pragma unroll
-  for (int p = 0; p < NV / 4; ++p) stage[(p + r * (NV / 4)) * 16 + c] = q[p];
+  for (int p = 0; p < NV / 4; ++p) stage[c * (NV + 1) + p + r * (NV / 4)] = q[p];
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   double tot = 0.0;
   if (lane < NV) {
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) tot += stage[lane * 16 + cc];
+    for (int cc = 0; cc < 16; ++cc) tot += stage[cc * (NV + 1) + lane];
     cross[w * NV + lane] = tot;
   }
   __syncthreads();

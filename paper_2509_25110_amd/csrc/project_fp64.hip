@@ -109,8 +109,8 @@ __global__ void __launch_bounds__(512) project_fp64_kernel(ProjectArgs a) {
   double *jms = lds + npad;                // [npad]  w j_m, later the Miller seed
   uint32_t *mps = (uint32_t *)(lds + 2 * npad);  // [npad]  (m + 1) | (sblk + 1) << 16
   double *const lds2 = lds + 2 * npad + (npad + 1) / 2;
-  double *stage = lds2 + w * NV * 16;      // per wave [NV][16]
-  double *cross0 = lds2 + W * NV * 16;     // [2][W][NV]
+  double *stage = lds2 + w * fp64::stage_doubles(NV);      // per wave [16][NV+1]
+  double *cross0 = lds2 + W * fp64::stage_doubles(NV);     // [2][W][NV]
   int *bnd = (int *)(cross0 + 2 * W * NV);       // [3]
 
   const double kk = a.k[ki];
@@ -431,7 +431,7 @@ ProjectShape project_fp64_shape(int nsrc, int64_t ntau, int force_waves, int for
   sh.slots = T;
   const int NV = kB * nsrc;
   const int npad = W * 64 * T;
-  sh.lds = sizeof(double) * ((size_t)2 * npad + (size_t)(npad + 1) / 2 + (size_t)W * NV * 16 +
+  sh.lds = sizeof(double) * ((size_t)2 * npad + (size_t)(npad + 1) / 2 + (size_t)W * fp64::stage_doubles(NV) +
                             2 * (size_t)W * NV) +
            4 * sizeof(int);
   return sh;

@@ -88,8 +88,8 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   double *ixs = lds;                                  // [npad] 1/x per node
   int *rs = (int *)(lds + npad);                      // [npad] top row R per node (-1: none)
   double *const lds2 = lds + npad + (npad + 1) / 2;
-  double *stage = lds2 + w * NV * 16;                 // per wave [NV][16]
-  double *cross0 = lds2 + W * NV * 16;                // [2][W][NV]
+  double *stage = lds2 + w * fp64::stage_doubles(NV);                 // per wave [16][NV+1]
+  double *cross0 = lds2 + W * fp64::stage_doubles(NV);                // [2][W][NV]
   int *bnd = (int *)(cross0 + 2 * W * NV);            // [1]
 
   const double kk = a.k[ki];
@@ -333,7 +333,7 @@ ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves, in
   sh.slots = T;
   const int NV = sh.block * nsrc;
   const int npad = W * 64 * T;
-  sh.lds = sizeof(double) * ((size_t)npad + (size_t)(npad + 1) / 2 + (size_t)W * NV * 16 +
+  sh.lds = sizeof(double) * ((size_t)npad + (size_t)(npad + 1) / 2 + (size_t)W * fp64::stage_doubles(NV) +
                             2 * (size_t)W * NV) +
            4 * sizeof(int) + lds_extra;
   return sh;
