@@ -230,8 +230,6 @@ def run_batch(args):
         "tile": [info["tile_mb"], info["tile_nc"]], "chunks": info["chunks"],
         "max_rel_err_vs_oracle": err,
     }
-    if interp is not None:
-        out["interp"] = interp
     if not args.no_cpu_baseline:
         import oracle
         m = 3

@@ -34,4 +34,55 @@ __device__ inline int ltop_of(double x) {
 // returns t*c - p.
 __device__ inline double rec_step(double t, double c, double p) { return fma(t, c, -p); }
 
+// Upward run from (p, q) = (f_{l0-1}, f_{l0}) to l1 >= l0: on return
+// (p, q) = (f_{l1-1}, f_{l1}).  The coefficient (2l+1)/x is formed exactly at
+// the start of every 8 steps and stepped by 2/x in between, with no per-step
+// test (a test per step is if-converted into a convert, a multiply and
+// selects on every step).
+__device__ inline void run_up(double &p, double &q, int l0, int l1, double ix) {
+  const double d2 = ix + ix;
+  int l = l0;
+  for (; l + 8 <= l1; l += 8) {
+    double t = (double)(2 * l + 1) * ix;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double r = rec_step(t, q, p);
+      t += d2;
+      p = q;
+      q = r;
+    }
+  }
+  double t = (double)(2 * l + 1) * ix;
+  for (; l < l1; ++l) {
+    const double r = rec_step(t, q, p);
+    t += d2;
+    p = q;
+    q = r;
+  }
+}
+
+// Downward run from (hn, hc) = (f_{l0+1}, f_{l0}) to l1 <= l0: on return
+// (hn, hc) = (f_{l1+1}, f_{l1}).  Coefficients as in run_up, stepped by -2/x.
+__device__ inline void run_down(double &hn, double &hc, int l0, int l1, double ix) {
+  const double d2 = ix + ix;
+  int l = l0;
+  for (; l - 8 >= l1; l -= 8) {
+    double t = (double)(2 * l + 1) * ix;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double h = rec_step(t, hc, hn);
+      t -= d2;
+      hn = hc;
+      hc = h;
+    }
+  }
+  double t = (double)(2 * l + 1) * ix;
+  for (; l > l1; --l) {
+    const double h = rec_step(t, hc, hn);
+    t -= d2;
+    hn = hc;
+    hc = h;
+  }
+}
+
 }  // namespace los

@@ -59,19 +59,8 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
       double s, c;
       sincos(x, &s, &c);
       double p = c * ix, q = s * ix;  // j_{l-1}, j_l at l = 0
-      // coefficient (2l+1)/x formed exactly every 8 steps, stepped by 2/x between
-      const double d2 = ix + ix;
       const int up = m >= a.lmax + 1 ? a.lmax + 1 : m;
-      {
-        double t = ix;
-        for (int l = 0; l < up; ++l) {
-          if ((l & 7) == 0) t = (double)(2 * l + 1) * ix;
-          const double r = rec_step(t, q, p);
-          t += d2;
-          p = q;
-          q = r;
-        }
-      }
+      run_up(p, q, 0, up, ix);
       if (m >= a.lmax + 1) {
         R = a.lmax;
         cur = wt * p;
@@ -79,20 +68,11 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
       } else {
         const double jm = q;
         R = min(L0, a.lmax);
-        double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l at l = L0
-        double hR = 1.0, hR1 = 0.0;
-        double t = 0.0;
-        for (int l = L0; l > m; --l) {
-          if (((L0 - l) & 7) == 0) t = (double)(2 * l + 1) * ix;
-          const double hp = rec_step(t, hc, hn);
-          t -= d2;
-          hn = hc;
-          hc = hp;
-          if (l - 1 == R) {
-            hR = hc;
-            hR1 = hn;
-          }
-        }
+        // Miller from (0, 1) at L0: on to the top row R, then on to m
+        double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l
+        run_down(hn, hc, L0, R, ix);
+        const double hR = hc, hR1 = hn;
+        run_down(hn, hc, R, m, ix);
         const double sc = wt * jm / hc;
         cur = sc * hR;
         nxt = sc * hR1;

@@ -116,30 +116,8 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         sincos(x, &sn, &cs);
         double p = wn * (cs * ix), q = wn * (sn * ix);  // w j_{-1}, w j_0
         const double fx = floor(x);
-        // upward runs: the coefficient (2l+1)/x is formed exactly every 8
-        // steps and stepped by 2/x in between (at most 7 rounding steps)
-        const double d2 = ix + ix;
         const int up = fx >= (double)(lmax + 1) ? lmax + 1 : (int)fx;
-        int l = 0;
-        for (; l + 8 <= up; l += 8) {
-          double t = (double)(2 * l + 1) * ix;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const double r = rec_step(t, q, p);
-            t += d2;
-            p = q;
-            q = r;
-          }
-        }
-        {
-          double t = (double)(2 * l + 1) * ix;
-          for (; l < up; ++l) {
-            const double r = rec_step(t, q, p);
-            t += d2;
-            p = q;
-            q = r;
-          }
-        }
+        run_up(p, q, 0, up, ix);
         if (fx >= (double)(lmax + 1)) {
           R = lmax;
           cur = p;  // w j_lmax
@@ -149,19 +127,11 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
           const double jm = q;  // w j_m
           const int L0 = ltop_of(x);
           R = L0 < lmax ? L0 : lmax;
-          double hn = 0.0, hc = 1.0, hR = 1.0, hR1 = 0.0;  // Miller from (0, 1) at L0
-          double t = (double)(2 * L0 + 1) * ix;
-          for (int ll = L0; ll > m; --ll) {
-            if (((L0 - ll) & 7) == 0) t = (double)(2 * ll + 1) * ix;
-            const double hp = rec_step(t, hc, hn);
-            t -= d2;
-            hn = hc;
-            hc = hp;
-            if (ll - 1 == R) {
-              hR = hc;
-              hR1 = hn;
-            }
-          }
+          // Miller from (0, 1) at L0: on to the top row R, then on to m
+          double hn = 0.0, hc = 1.0;
+          run_down(hn, hc, L0, R, ix);
+          const double hR = hc, hR1 = hn;
+          run_down(hn, hc, R, m, ix);
           const double sc = jm / hc;
           cur = sc * hR;
           nxt = sc * hR1;
@@ -221,37 +191,47 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   int parity = 0;
   // with E-mode limit terms, block 0 is swept even when no node reaches it
   const int first = (a.emask != 0 && lmin == 2 && top_blk < 0) ? 0 : top_blk;
+  // Sources of the fully-live slots come through a ring of 4 register sets:
+  // slot j uses ring[j % 4] and is loaded 3 slots ahead.  S does not depend
+  // on the row block, so the last slots of a block prefetch the first slots
+  // of the next one (T is a multiple of 4, so slot j keeps its ring entry).
+  double ring[4][NSRC];
+  if (first >= 0) {
+    const uint64_t fm0 = slot_mask(thF >= first);
+#pragma unroll
+    for (int j = 0; j < 3 && j < T; ++j)
+      if (has(fm0, j)) load_s<NSRC>(ring[j], srow, (w + W * j) * 64 + lane, ntau);
+  }
   for (int bi = first; bi >= 0; --bi) {
     const int b = lmin + bi * B;
     const int top = b + B - 1;
     const uint64_t fm = slot_mask(thF >= bi);        // all lanes live through the block
     const uint64_t pm = slot_mask(thA >= bi) & ~fm;  // some lanes start inside it
+    const uint64_t fmn = bi > 0 ? slot_mask(thF >= bi - 1) : 0;  // the next block's
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    {
-      double sv[NSRC], svn[NSRC];
-      load_s<NSRC>(sv, srow, w * 64 + lane, ntau);
 #pragma unroll
-      for (int j = 0; j < T; ++j) {
-        const int nb = (w + W * j) * 64;
-        if (nb >= ntau) break;
-        int n = nb + lane;
-        asm volatile("" : "+v"(n));
-        if (j + 1 < T) load_s<NSRC>(svn, srow, n + W * 64, ntau);
-        if (has(fm, j)) {
-          const double ix = ixs[n];
-          if (a.emask != 0) {  // uniform
-            const double i2 = ix * ix;
-#pragma unroll
-            for (int s = 0; s < NSRC; ++s)
-              if ((a.emask >> s) & 1u) sv[s] *= i2;
-          }
-          sweep_slot<NSRC, B, false>(acc, Jn[j], Jc[j], ix, sv, top, 0);
-        }
-#pragma unroll
-        for (int s = 0; s < NSRC; ++s) sv[s] = svn[s];
+    for (int j = 0; j < T; ++j) {
+      {
+        const int jp = j + 3;  // prefetch: this block's slot jp or the next block's jp - T
+        const int js = jp < T ? jp : jp - T;
+        if (has(jp < T ? fm : fmn, js))
+          load_s<NSRC>(ring[js % 4], srow, (w + W * js) * 64 + lane, ntau);
       }
+      const int nb = (w + W * j) * 64;
+      if (nb >= ntau || !has(fm, j)) continue;
+      int n = nb + lane;
+      asm volatile("" : "+v"(n));
+      double(&sv)[NSRC] = ring[j % 4];
+      const double ix = ixs[n];
+      if (a.emask != 0) {  // uniform; the ring entry is reloaded before its next use
+        const double i2 = ix * ix;
+#pragma unroll
+        for (int s = 0; s < NSRC; ++s)
+          if ((a.emask >> s) & 1u) sv[s] *= i2;
+      }
+      sweep_slot<NSRC, B, false>(acc, Jn[j], Jc[j], ix, sv, top, 0);
     }
 #pragma unroll
     for (int j = 0; j < T; ++j) {
