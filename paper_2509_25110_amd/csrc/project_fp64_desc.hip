@@ -5,19 +5,23 @@
 //
 // Same workgroup / wave / slot mapping and per-block reduction as
 // project_fp64.hip, but every lane walks its l range once, from the top down:
-//   * setup: each node finds w (j_R, j_{R+1}) at its top row
-//     R = min(ltop(x), lmax).  For x >= lmax + 1 the upward recurrence from
-//     j_{-1} = cos x / x, j_0 = sin x / x runs to lmax + 1 (stable on the
-//     oscillatory side); otherwise it runs to m = floor(x) for j_m, and
-//     Miller's recurrence from ltop(x) with seeds (0, 1) runs down to m and is
-//     scaled there to j_m (j_m is near the last maximum in l, never near a
-//     zero), giving the pair at R;
+//   * setup: each node finds w (j_R, j_{R+1}) at its top row R, the top row
+//     of the B-row block that holds min(ltop(x), lmax).  For x >= lmax + 1
+//     the upward recurrence from j_{-1} = cos x / x, j_0 = sin x / x runs to
+//     R + 1 (stable on the oscillatory side; R is at most B - 1 rows past
+//     lmax, and those rows are never stored); otherwise it runs to
+//     m = floor(x) for j_m, and Miller's recurrence with seeds (0, 1) from
+//     max(ltop(x), R) runs down to m and is scaled there to j_m (j_m is near
+//     the last maximum in l, never near a zero), giving the pair at R.  Rows
+//     between ltop(x) and R carry values below the band cut.
 //   * the sweep: blocks of B = 16 rows (8 selectable) from the highest top of
-//     the workgroup down to lmin; each lane runs j_{l-1} = (2l+1)/x j_l - j_{l+1} for its
-//     slots, rows above its R contributing 0.  Downward is the stable
-//     direction above the turning point and neutrally stable below it, so one
-//     sweep covers the whole band with no second pass and no read-modify-write
-//     of delta.
+//     the workgroup down to lmin; each lane runs j_{l-1} = (2l+1)/x j_l -
+//     j_{l+1} for its slots from its R down.  R being a block top, a lane is
+//     live either throughout a block or not at all, so a slot whose lanes
+//     start in different blocks runs the same code under an exec mask.
+//     Downward is the stable direction above the turning point and neutrally
+//     stable below it, so one sweep covers the whole band with no second pass
+//     and no read-modify-write of delta.
 // E-mode sources (bit s of emask; Sec. 2.1, Eq. 3: eps_l(x) =
 // sqrt((l+2)!/(l-2)!) j_l(x) / x^2): their values are scaled by 1/x^2 per node
 // as they are loaded and their output rows by sqrt((l-1) l (l+1) (l+2)); a node
@@ -39,11 +43,10 @@ using fp64::wave_min;
 using fp64::wg_reduce;
 
 // One slot over the block of rows top .. top-B+1, descending.  (p1, p0) =
-// (w j_{l+1}, w j_l) at l = top on entry.  With MASK, only rows l <= R are
-// live (rel = R - (top - B + 1)); the others output 0 and leave the state.
-template <int NSRC, int B, bool MASK>
+// (w j_{l+1}, w j_l) at l = top on entry, at l = top - B on return.
+template <int NSRC, int B>
 __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, double &p0,
-                                           double ix, const double (&sv)[NSRC], int top, int rel) {
+                                           double ix, const double (&sv)[NSRC], int top) {
   double t = 0.0;
   const double d2 = ix + ix;
 #pragma unroll
@@ -51,23 +54,12 @@ __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, 
     // the coefficient (2l+1)/x is formed exactly every 8 rows and stepped by
     // -2/x in between (at most 7 rounding steps, whatever the block size)
     if (i % 8 == 0) t = (double)(2 * (top - i) + 1) * ix;
-    // row l = top - i is live when l <= R, i.e. i >= top - R = (B - 1) - rel
     const int q = (B - 1 - i) * NSRC;
-    if (MASK) {
-      const bool live = i >= (B - 1) - rel;
-      const double o = live ? p0 : 0.0;
 #pragma unroll
-      for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(o, sv[s], acc[q + s]);
-      const double nx = rec_step(t, p0, p1);
-      p1 = live ? p0 : p1;
-      p0 = live ? nx : p0;
-    } else {
-#pragma unroll
-      for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
-      const double nx = rec_step(t, p0, p1);
-      p1 = p0;
-      p0 = nx;
-    }
+    for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
+    const double nx = rec_step(t, p0, p1);
+    p1 = p0;
+    p0 = nx;
     t -= d2;
   }
 }
@@ -99,6 +91,11 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
 
   // ---------------- per-node setup: the pair at the top row ----------------
   double Jn[T], Jc[T];  // w j_{l+1}, w j_l of the current row, per slot
+  // Every node's top row R is the top row of a block (the block holding its
+  // band edge or lmax), so in any block a lane is either live throughout or
+  // not at all.  Rows between the band edge and R hold values below the band
+  // cut; rows above lmax are swept but never stored.
+  const int top_all = lmin + (lmax - lmin) / B * B + (B - 1);
   // Per-slot block thresholds held by lane j for slot j (wave-uniform):
   // the slot runs unmasked in blocks bi <= thF and at all in blocks bi <= thA.
   int thF = -1, thA = -1, my_top = -1;
@@ -116,27 +113,32 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         sincos(x, &sn, &cs);
         double p = wn * (cs * ix), q = wn * (sn * ix);  // w j_{-1}, w j_0
         const double fx = floor(x);
-        const int up = fx >= (double)(lmax + 1) ? lmax + 1 : (int)fx;
-        run_up(p, q, 0, up, ix);
         if (fx >= (double)(lmax + 1)) {
-          R = lmax;
-          cur = p;  // w j_lmax
-          nxt = q;  // w j_{lmax+1}
+          // upward to the top row of the block holding lmax (at most B - 1
+          // rows past it; those rows are swept but never stored)
+          R = top_all;
+          run_up(p, q, 0, R + 1, ix);
+          cur = p;  // w j_R
+          nxt = q;  // w j_{R+1}
         } else {
-          const int m = up;
+          const int m = (int)fx;
+          run_up(p, q, 0, m, ix);
           const double jm = q;  // w j_m
           const int L0 = ltop_of(x);
-          R = L0 < lmax ? L0 : lmax;
-          // Miller from (0, 1) at L0: on to the top row R, then on to m
-          double hn = 0.0, hc = 1.0;
-          run_down(hn, hc, L0, R, ix);
-          const double hR = hc, hR1 = hn;
-          run_down(hn, hc, R, m, ix);
-          const double sc = jm / hc;
-          cur = sc * hR;
-          nxt = sc * hR1;
+          const int Rc = L0 < lmax ? L0 : lmax;  // last row kept (band edge or lmax)
+          if (Rc >= lmin) {
+            // top row of the block holding Rc; Miller starts at or above it
+            R = lmin + (Rc - lmin) / B * B + (B - 1);
+            const int Ls = L0 > R ? L0 : R;
+            double hn = 0.0, hc = 1.0;  // Miller seeds (0, 1) at Ls
+            run_down(hn, hc, Ls, R, ix);
+            const double hR = hc, hR1 = hn;
+            run_down(hn, hc, R, m, ix);
+            const double sc = jm / hc;
+            cur = sc * hR;
+            nxt = sc * hR1;
+          }
         }
-        if (R < lmin) R = -1;
       }
     }
     ixs[n] = ix;
@@ -231,7 +233,7 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         for (int s = 0; s < NSRC; ++s)
           if ((a.emask >> s) & 1u) sv[s] *= i2;
       }
-      sweep_slot<NSRC, B, false>(acc, Jn[j], Jc[j], ix, sv, top, 0);
+      sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ix, sv, top);
     }
 #pragma unroll
     for (int j = 0; j < T; ++j) {
@@ -248,9 +250,8 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
           for (int s = 0; s < NSRC; ++s)
             if ((a.emask >> s) & 1u) sv[s] *= i2;
         }
-        int rel = rs[n] - b;  // rows b .. b + rel are live (rel < 0: none)
-        asm volatile("" : "+v"(rel));
-        sweep_slot<NSRC, B, true>(acc, Jn[j], Jc[j], ixs[n], sv, top, rel);
+        if (rs[n] >= top)  // this lane is live through the block (R is a block top)
+          sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ixs[n], sv, top);
       }
     }
     if (bi == 0) {  // row l = lmin: the x -> 0 E-mode terms (zero unless emask and lmin = 2)
