@@ -4,13 +4,15 @@
 //   J_k[l][n] = w_n * j_l(k * (tau0 - tau_n)),   so   Delta_k = J_k . S_k
 //
 // One lane per tau node, one workgroup column per k.  Each lane first finds
-// a normalised pair (J_R, J_{R+1}) at its top row R = min(ltop(x), lmax):
+// a normalised pair (J_R, J_{R+1}) at its top row R, the top row of the
+// 16-row block holding min(ltop(x), lmax):
 //   * x >= lmax + 1: upward recurrence from j_0 = sin x / x, j_{-1} = cos x / x
-//     (stable on the oscillatory side) up to l = lmax + 1;
+//     (stable on the oscillatory side) up to l = R + 1;
 //   * otherwise: upward to m = floor(x) for j_m, and Miller's downward
-//     recurrence from ltop(x) with seeds (0, 1) down to m; the Miller values
-//     are scaled by j_m / J^_m.
-// It then runs the recurrence DOWNWARD from R to lmin, writing every row.
+//     recurrence from max(ltop(x), R) with seeds (0, 1) down to m; the Miller
+//     values are scaled by j_m / J^_m.
+// It then runs the recurrence DOWNWARD from R to lmin, writing every row
+// (a whole 16-row block at a time: zeros in blocks above R).
 // Downward is the stable direction above the turning point and neutrally
 // stable below it (both solutions oscillate with equal amplitude there), so
 // a single descending sweep covers the whole band.
@@ -59,25 +61,31 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
       double s, c;
       sincos(x, &s, &c);
       double p = c * ix, q = s * ix;  // j_{l-1}, j_l at l = 0
-      const int up = m >= a.lmax + 1 ? a.lmax + 1 : m;
-      run_up(p, q, 0, up, ix);
+      // R is the top row of the 16-row block holding min(ltop(x), lmax): a lane
+      // is then live either throughout a block or not at all.  Rows between
+      // the band edge and R hold values below the band cut; rows past lmax
+      // (at most 15, inside the padded table) are never stored by the product.
       if (m >= a.lmax + 1) {
-        R = a.lmax;
+        R = a.lmin + (a.lmax - a.lmin) / 16 * 16 + 15;
+        run_up(p, q, 0, R + 1, ix);
         cur = wt * p;
         nxt = wt * q;
       } else {
+        run_up(p, q, 0, m, ix);
         const double jm = q;
-        R = min(L0, a.lmax);
-        // Miller from (0, 1) at L0: on to the top row R, then on to m
-        double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l
-        run_down(hn, hc, L0, R, ix);
-        const double hR = hc, hR1 = hn;
-        run_down(hn, hc, R, m, ix);
-        const double sc = wt * jm / hc;
-        cur = sc * hR;
-        nxt = sc * hR1;
+        const int Rc = min(L0, a.lmax);
+        if (Rc >= a.lmin) {
+          R = a.lmin + (Rc - a.lmin) / 16 * 16 + 15;
+          // Miller from (0, 1) at max(L0, R): on to the top row R, then on to m
+          double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l
+          run_down(hn, hc, max(L0, R), R, ix);
+          const double hR = hc, hR1 = hn;
+          run_down(hn, hc, R, m, ix);
+          const double sc = wt * jm / hc;
+          cur = sc * hR;
+          nxt = sc * hR1;
+        }
       }
-      if (R < a.lmin) R = -1;
     }
   }
 
@@ -91,23 +99,24 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
 
   if (n >= a.ntp) return;  // no column of its own (after the shuffles above)
   float *col = a.J + (int64_t)ki * a.nlp * a.ntp + n;
+  const double d2 = ix + ix;
   for (int b = tb_wave; b >= 0; --b) {
     const int lbase = a.lmin + 16 * b;
     float *dst = col + (int64_t)(16 * b) * a.ntp;
-    double t = 0.0;
+    if (R >= lbase + 15) {  // live through the block
+      double t = 0.0;
 #pragma unroll
-    for (int r = 15; r >= 0; --r) {
-      const int l = lbase + r;
-      if (r == 15 || r == 7) t = (double)(2 * l + 1) * ix;  // exact every 8 rows
-      float v = 0.f;
-      if (l <= R) {
-        v = (float)cur;
+      for (int r = 15; r >= 0; --r) {
+        if (r == 15 || r == 7) t = (double)(2 * (lbase + r) + 1) * ix;  // exact every 8 rows
+        dst[(int64_t)r * a.ntp] = (float)cur;
         const double pv = rec_step(t, cur, nxt);
         nxt = cur;
         cur = pv;
+        t -= d2;
       }
-      t -= ix + ix;
-      dst[(int64_t)r * a.ntp] = v;
+    } else {
+#pragma unroll
+      for (int r = 15; r >= 0; --r) dst[(int64_t)r * a.ntp] = 0.f;
     }
   }
 }
