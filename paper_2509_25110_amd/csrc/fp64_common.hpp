@@ -40,22 +40,12 @@ __device__ inline double swap_add16(double a, double b) {
 // of LDS bank conflicts).
 constexpr int stage_doubles(int NV) { return 16 * (NV + 1); }
 
-// Reduce v[NV] over the workgroup's lanes.  On return, lane L < NV of wave 0
-// holds the total of index L (other lanes: unspecified).  `stage` is this
-// wave's [16][NV + 1] LDS area, `cross` the [W][NV] area of the current parity.
+// Reduce v[NV] over one wave's lanes.  On return, lane L < NV holds the
+// wave's total of index L (other lanes: unspecified).  `stage` is this wave's
+// [16][NV + 1] LDS area.
 template <int NV>
-__device__ inline double wg_reduce(double (&v)[NV], double *stage, double *cross, int W, int w,
-                                   int lane, bool wave_active = true) {
+__device__ inline double wave_reduce(double (&v)[NV], double *stage, int lane) {
   static_assert(NV % 4 == 0, "NV must be a multiple of 4");
-  if (!wave_active) {  // uniform: this wave contributed nothing to the block
-    if (lane < NV) cross[w * NV + lane] = 0.0;
-    __syncthreads();
-    double all = 0.0;
-    if (w == 0 && lane < NV) {
-      for (int ww = 0; ww < W; ++ww) all += cross[ww * NV + lane];
-    }
-    return all;
-  }
   double u[NV / 2];
 #pragma unroll
   for (int p = 0; p < NV / 2; ++p) u[p] = swap_add32(v[p], v[p + NV / 2]);
@@ -71,7 +61,21 @@ __device__ inline double wg_reduce(double (&v)[NV], double *stage, double *cross
   if (lane < NV) {
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) tot += stage[cc * (NV + 1) + lane];
-    cross[w * NV + lane] = tot;
+  }
+  return tot;
+}
+
+// Reduce v[NV] over the workgroup's lanes.  On return, lane L < NV of wave 0
+// holds the total of index L (other lanes: unspecified).  `stage` is this
+// wave's [16][NV + 1] LDS area, `cross` the [W][NV] area of the current parity.
+template <int NV>
+__device__ inline double wg_reduce(double (&v)[NV], double *stage, double *cross, int W, int w,
+                                   int lane, bool wave_active = true) {
+  if (!wave_active) {  // uniform: this wave contributed nothing to the block
+    if (lane < NV) cross[w * NV + lane] = 0.0;
+  } else {
+    const double tot = wave_reduce<NV>(v, stage, lane);
+    if (lane < NV) cross[w * NV + lane] = tot;
   }
   __syncthreads();
   double all = 0.0;

@@ -40,7 +40,7 @@ using fp64::load_s;
 using fp64::slot_mask;
 using fp64::wave_max;
 using fp64::wave_min;
-using fp64::wg_reduce;
+using fp64::wave_reduce;
 
 // One slot over the block of rows top .. top-B+1, descending.  (p1, p0) =
 // (w j_{l+1}, w j_l) at l = top on entry, at l = top - B on return.
@@ -81,8 +81,8 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   int *rs = (int *)(lds + npad);                      // [npad] top row R per node (-1: none)
   double *const lds2 = lds + npad + (npad + 1) / 2;
   double *stage = lds2 + w * fp64::stage_doubles(NV);                 // per wave [16][NV+1]
-  double *cross0 = lds2 + W * fp64::stage_doubles(NV);                // [2][W][NV]
-  int *bnd = (int *)(cross0 + 2 * W * NV);            // [1]
+  double *cross = lds2 + W * fp64::stage_doubles(NV);  // [8][W][NV] ring of block partials
+  int *bnd = (int *)(cross + 8 * W * NV);              // [1]
 
   const double kk = a.k[ki];
   const double *srow[NSRC];
@@ -190,7 +190,6 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
       if (b + lane / NSRC <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] = 0.0;
     }
   }
-  int parity = 0;
   // with E-mode limit terms, block 0 is swept even when no node reaches it
   const int first = (a.emask != 0 && lmin == 2 && top_blk < 0) ? 0 : top_blk;
   // Sources of the fully-live slots come through a ring of 4 register sets:
@@ -258,13 +257,25 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
 #pragma unroll
       for (int s = 0; s < NSRC; ++s) acc[s] += e2[s];
     }
-    double tot = wg_reduce<NV>(acc, stage, cross0 + parity * W * NV, W, w, lane);
-    parity ^= 1;
-    if (w == 0 && lane < NV) {
-      const int l = b + lane / NSRC;
-      if ((a.emask >> (lane % NSRC)) & 1u)
-        tot *= sqrt((double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2));
-      if (l <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] = tot;
+    // Each wave leaves its block total in ring slot bi % 8; every 4 blocks
+    // (bi % 4 == 0) the workgroup synchronises once and wave 0 sums the waves
+    // in a fixed order and stores those blocks, while the other waves go on
+    // into the other half of the ring.
+    const double part = wave_reduce<NV>(acc, stage, lane);
+    if (lane < NV) cross[((bi & 7) * W + w) * NV + lane] = part;
+    if ((bi & 3) == 0) {
+      __syncthreads();
+      if (w == 0 && lane < NV) {
+        const int hi = bi + 3 < first ? bi + 3 : first;
+        for (int bb = hi; bb >= bi; --bb) {
+          double tot = 0.0;
+          for (int ww = 0; ww < W; ++ww) tot += cross[((bb & 7) * W + ww) * NV + lane];
+          const int l = lmin + bb * B + lane / NSRC;
+          if ((a.emask >> (lane % NSRC)) & 1u)
+            tot *= sqrt((double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2));
+          if (l <= lmax) drow[(int64_t)(bb * B) * NSRC + lane] = tot;
+        }
+      }
     }
   }
 }
@@ -315,7 +326,7 @@ ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves, in
   const int NV = sh.block * nsrc;
   const int npad = W * 64 * T;
   sh.lds = sizeof(double) * ((size_t)npad + (size_t)(npad + 1) / 2 + (size_t)W * fp64::stage_doubles(NV) +
-                            2 * (size_t)W * NV) +
+                            8 * (size_t)W * NV) +
            4 * sizeof(int) + lds_extra;
   return sh;
 }
