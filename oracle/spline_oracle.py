@@ -84,6 +84,22 @@ def evaluate(q, Sc, M, k) -> np.ndarray:
             + cA[None, :, None] * M[:, j, :] + cB[None, :, None] * M[:, j + 1, :])
 
 
+def interp_cl(ls, cls, lmin, lmax) -> np.ndarray:
+    """C_l at every l in [lmin, lmax] from cls[npairs, len(ls)] at the sampled multipoles ls
+    (the output l-sampling of the gCAMB paper, Sec. 3.1, read as the natural cubic spline
+    in l of D_l = l (l + 1) C_l through the sampled points, divided back by l (l + 1))."""
+    ls = np.asarray(ls, dtype=np.float64)
+    cls = np.atleast_2d(np.asarray(cls, dtype=np.float64))
+    if ls[0] != lmin or ls[-1] != lmax:
+        raise ValueError("the sampled multipoles must include lmin and lmax")
+    ell = np.arange(lmin, lmax + 1, dtype=np.float64)
+    if ls.size == 1:
+        return cls.copy()
+    D = cls * (ls * (ls + 1.0))[None, :]
+    Dall = interpolate(ls, D[:, :, None], ell)[:, :, 0]
+    return Dall / (ell * (ell + 1.0))[None, :]
+
+
 def interpolate(q, Sc, k) -> np.ndarray:
     """Sources on the projection grid: evaluate(q, Sc, second_derivatives(q, Sc), k)."""
     return evaluate(q, Sc, second_derivatives(q, Sc), k)

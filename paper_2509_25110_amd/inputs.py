@@ -166,6 +166,20 @@ def coarse_sources(wl: Workload, nkc: int) -> CoarseSources:
     return CoarseSources(q=q, Sc=sources(q, wl.tau, wl.nsrc, **kw))
 
 
+def l_samples(lmin: int, lmax: int, boost: float = 1.0) -> np.ndarray:
+    """Multipoles computed explicitly at an output sampling density `boost`: from lmin,
+    steps of round(0.1 l / boost) clipped to [1, max(1, round(50 / boost))], always
+    ending at lmax.  boost = 50 (or any boost >= 50) samples every l."""
+    if lmax < lmin:
+        raise ValueError("lmax < lmin")
+    cap = max(1, int(round(50.0 / boost)))
+    out = [lmin]
+    while out[-1] < lmax:
+        step = min(max(1, int(round(0.1 * out[-1] / boost))), cap)
+        out.append(min(out[-1] + step, lmax))
+    return np.asarray(out, dtype=np.int32)
+
+
 def small(lmax=40, nk=24, kmax=0.02, ntau=200, nsrc=3, kmin=1e-4, **kw) -> Workload:
     """A small workload of the same structure (for quick parity tests)."""
     return _make("small", lmax=lmax, nk=nk, kmax=kmax, ntau=ntau, nsrc=nsrc, kmin=kmin, **kw)

@@ -107,3 +107,33 @@ def test_rejects_bad_grids():
         so.second_derivatives(np.array([0.0, 1.0, 1.0]), np.zeros((1, 3, 1)))
     with pytest.raises(ValueError):
         so.second_derivatives(np.array([0.0]), np.zeros((1, 1, 1)))
+
+
+def test_interp_cl_pins():
+    """C_l interpolation over sampled multipoles: exact at the samples, the identity when
+    every l is sampled, and exact for D_l = l (l+1) C_l linear in l (a natural spline
+    reproduces lines), which pins the l (l+1) scaling on both sides."""
+    from paper_2509_25110_amd import inputs
+    rng = np.random.default_rng(21)
+    lmin, lmax = 2, 300
+    ls = inputs.l_samples(lmin, lmax, 1.0)
+    cls = rng.uniform(0.5, 2.0, size=(3, ls.size))
+    out = so.interp_cl(ls, cls, lmin, lmax)
+    np.testing.assert_allclose(out[:, ls - lmin], cls, rtol=1e-14, atol=0)
+    full = np.arange(lmin, lmax + 1)
+    allc = rng.uniform(size=(2, full.size))
+    np.testing.assert_allclose(so.interp_cl(full, allc, lmin, lmax), allc, rtol=1e-14, atol=0)
+    ell = full.astype(float)
+    lin = (3.0 * ell + 7.0) / (ell * (ell + 1.0))
+    got = so.interp_cl(ls, lin[ls - lmin][None, :], lmin, lmax)[0]
+    np.testing.assert_allclose(got, lin, rtol=1e-12, atol=0)
+
+
+def test_l_samples_rule():
+    from paper_2509_25110_amd import inputs
+    a = inputs.l_samples(2, 2500, 1.0)
+    assert a[0] == 2 and a[-1] == 2500 and np.all(np.diff(a) >= 1)
+    assert np.max(np.diff(a)) == 50 and np.all(np.diff(a)[:10] == 1)
+    assert 80 < a.size < 150
+    assert np.array_equal(inputs.l_samples(2, 2500, 50.0), np.arange(2, 2501))
+    assert inputs.l_samples(7, 7, 1.0).tolist() == [7]
