@@ -35,20 +35,24 @@ GOLDEN = {"C2": os.path.join(ROOT, "tests", "golden", "c2_cl_oracle.txt"),
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
-def tp_and_band_counts(wl):
+def tp_and_band_counts(wl, ls=None):
     """Per-launch work counts over all (k, tau) pairs (host-side counting only).
     TP: l in [lmin, lmax] with x = k (tau0 - tau) >= l + 1/2 (the oscillatory, threshold-free set).
-    band: l up to the kernel's cut x + 14.2 x^(1/3) + 9.5."""
+    band: l up to the kernel's cut x + 14.2 x^(1/3) + 9.5.  With a sorted multipole list `ls`,
+    also the TP entries whose l is in it."""
     chi = wl.tau0 - wl.tau
     tp = 0
     band = 0
+    tps = 0
     for i in range(0, wl.nk, 256):
         x = wl.k[i:i + 256, None] * chi[None, :]
         top = np.minimum(np.floor(x - 0.5), wl.lmax)
         tp += int(np.sum(np.maximum(top - wl.lmin + 1, 0)))
         cut = np.minimum(np.floor(x + 14.2 * np.cbrt(x) + 9.5), wl.lmax)
         band += int(np.sum(np.maximum(cut - wl.lmin + 1, 0)))
-    return tp, band
+        if ls is not None:
+            tps += int(np.sum(np.searchsorted(ls, top, side="right")))
+    return (tp, band, tps) if ls is not None else (tp, band)
 
 
 def fp64_kernel():
@@ -434,6 +438,9 @@ def main():
     ap.add_argument("--emu-epochs", type=int, default=300, help="C5: training epochs")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="C4: also time the FP64 plain path on a sample of the batch's models")
+    ap.add_argument("--lsample", type=float, default=0.0,
+                    help="C2/C3 FP64: compute the multipoles of inputs.l_samples(boost) only and "
+                         "interpolate C_l (los_project_lsample + cl_integrate + los_cl_interp)")
     ap.add_argument("--interp", action="store_true",
                     help="C1-C3: sources on the coarse k grid, splined onto the LOS grid each step")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -484,10 +491,32 @@ def main():
             ctx.los_spline_sources(q, Sc, M=M)
             ctx.los_interp_sources(q, Sc, M, k, out_prec=0 if prec == 0 else 1, S=S)
 
+    ls = None
+    if args.lsample > 0:
+        if prec != 0:
+            print("bench.py: --lsample runs the FP64 path only", file=sys.stderr)
+            sys.exit(2)
+        ls = inputs.l_samples(wl.lmin, wl.lmax, args.lsample)
+        delta = torch.empty((wl.nk, ls.size, wl.nsrc), dtype=torch.float64, device="cuda")
+        cls = torch.empty((len(wl.pairs), ls.size), dtype=torch.float64, device="cuda")
+
+    def project():
+        if ls is None:
+            ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
+        else:
+            ctx.los_project_lsample(wl.lmin, wl.lmax, ls, k, tau, wl.tau0, w, S, delta=delta)
+
+    def spectra():
+        if ls is None:
+            ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
+        else:
+            ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cls)
+            ctx.los_cl_interp(ls, cls, wl.lmin, wl.lmax, cl=cl)
+
     def step():
         prepare()
-        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
-        ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
+        project()
+        spectra()
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -510,9 +539,9 @@ def main():
         evi[i].record(stream)
         prepare()
         ev[i][0].record(stream)
-        ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
+        project()
         ev[i][1].record(stream)
-        ctx.cl_integrate(delta, wk, Pk, wl.pairs, cl=cl)
+        spectra()
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -521,11 +550,21 @@ def main():
     prep_ms = float(np.mean([a.elapsed_time(b[0]) for a, b in zip(evi, ev)]))
     ms_per_step = total_ms / K
 
-    tp, band = tp_and_band_counts(wl)
-    flops = tp * (3.0 + 2.0 * wl.nsrc)  # recurrence FMA + coefficient add, nsrc FMAs, per TP entry
+    if ls is None:
+        tp, band = tp_and_band_counts(wl)
+        flops = tp * (3.0 + 2.0 * wl.nsrc)  # recurrence FMA + coefficient add, nsrc FMAs, per TP entry
+    else:  # the recurrence at every TP entry, the accumulation at the sampled ones
+        tp, band, tps = tp_and_band_counts(wl, ls)
+        flops = tp * 3.0 + tps * 2.0 * wl.nsrc
     achieved = flops / (proj_ms * 1e-3) / 1e12
     gfma = wl.nsrc * tp / (ms_per_step * 1e-3) / 1e9
     err = golden_error(cl.cpu().numpy(), wl)
+    lsample = None
+    if ls is not None:
+        lsample = {"boost": args.lsample, "nls": int(ls.size),
+                   "cl_rel_dev_vs_all_l": err,
+                   "tp_sampled_entries": tps}
+        err = None  # the interpolated C_l differ from the all-l ones by the interpolation
     interp = None
     if args.interp:
         nkc = cs.q.size
@@ -560,9 +599,12 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": traffic_for(prec, wl),
+                     "traffic": traffic_for(prec, wl) if ls is None else None,
                      "kernel": kernel, "kernel_ms": proj_ms,
-                     "work": "%d TP (l,k,tau) entries x %d FP64 flops" % (tp, 3 + 2 * wl.nsrc)},
+                     "work": ("%d TP (l,k,tau) entries x %d FP64 flops" % (tp, 3 + 2 * wl.nsrc)
+                              if ls is None else
+                              "%d TP entries x 3 + %d sampled TP entries x %d FP64 flops"
+                              % (tp, tps, 2 * wl.nsrc))},
         "gfma_per_s": gfma,
         "tp_entries": tp,
         "band_entries": band,
@@ -573,7 +615,11 @@ def main():
     }
     if interp is not None:
         out["interp"] = interp
-    if not args.no_cpu_baseline and rank == 0 and not args.interp:
+    if lsample is not None:
+        out["lsample"] = lsample
+        out["config"]["workload"] += ", multipoles of l_samples(boost=%g) (%d), C_l interpolated" % (
+            args.lsample, ls.size)
+    if not args.no_cpu_baseline and rank == 0 and not args.interp and ls is None:
         stride = args.cpu_stride or {"C3": 4}.get(wl.name, 1)
         out["cpu_baseline"] = cpu_baseline(wl, stride)
     ctx.close()

@@ -165,6 +165,42 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
                  int32_t npairs, double *cl, void *stream);
 
 /*
+ * Multipole sampling (Sec. 3.1: the output l-sampling density sets how many
+ * multipoles are computed explicitly; the others are interpolated).
+ *
+ * los_project_lsample: the FP64 projection (as los_project_kernels with
+ *   prec LOS_FP64) at the multipoles ls[0..nls-1] only:
+ *     delta[(i * nls + j) * nsrc + s] = Delta^s_{ls[j]}(k_i).
+ *   ls: HOST, nls int32 strictly increasing within [lmin, lmax],
+ *   1 <= nls <= lmax - lmin + 1.  The Bessel recurrence still walks every
+ *   multipole (it needs them all); the accumulation, the reduction and the
+ *   stores happen at the sampled ones only.  Other arguments, limits and
+ *   kernel_mask as for los_project_kernels.  The row tables built from ls are
+ *   kept in the context; a call with a different list than the previous one
+ *   waits for the work queued on `stream` before replacing them.
+ *
+ * los_cl_interp: C_l at every l in [lmin, lmax] from its values at ls:
+ *     cl[p * (lmax - lmin + 1) + l - lmin] = D_p(l) / (l (l + 1)),
+ *   D_p the natural cubic spline in l (zero second derivative at both ends)
+ *   through the points (ls[j], ls[j] (ls[j] + 1) cls[p * nls + j]).
+ *   ls: HOST, strictly increasing, ls[0] = lmin, ls[nls-1] = lmax,
+ *   1 <= nls <= 2048; cls: device, npairs*nls doubles (cl_integrate's output
+ *   for the sampled delta); cl: device, npairs*(lmax-lmin+1) doubles, distinct
+ *   from cls.  1 <= npairs <= 65535.  The knots are kept in the context as for
+ *   los_project_lsample.
+ *
+ * Errors: LOS_ERR_INVALID for NULL pointers, bad lists or sizes;
+ * LOS_ERR_UNSUPPORTED when the two-pass FP64 scheme is selected
+ * (LOS_PROJ_SCHEME=0) or no launch shape fits ntau.
+ */
+int los_project_lsample(los_ctx *ctx, int32_t lmin, int32_t lmax, const int32_t *ls,
+                        int32_t nls, int64_t nk, int64_t ntau, double tau0, const double *k,
+                        const double *tau, const double *w_tau, const double *S, int32_t nsrc,
+                        uint32_t kernel_mask, double *delta, void *stream);
+int los_cl_interp(los_ctx *ctx, int32_t npairs, const int32_t *ls, int32_t nls,
+                  const double *cls, int32_t lmin, int32_t lmax, double *cl, void *stream);
+
+/*
  * Source preparation (Sec. 3.2: before the integrals, InterpolateSources
  * brings the source data onto the integration grid; the paper names the step
  * but not its scheme).  Here the sources are given on a coarse wavenumber

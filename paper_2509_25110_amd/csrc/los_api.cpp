@@ -10,18 +10,23 @@
 #include <cstdio>
 #include <cstdlib>
 #include <string>
+#include <vector>
 
 #include "los_internal.hpp"
 
 // Workspace slots of a context: the C_l partial sums and the Bessel tables
 // of the MFMA projection live in separate buffers, so a C_l call queued
 // behind a projection never reallocates memory the projection still reads.
-enum { WS_CL = 0, WS_JTAB = 1, WS_SPLINE = 2, WS_COUNT = 3 };
+enum { WS_CL = 0, WS_JTAB = 1, WS_SPLINE = 2, WS_LSEL = 3, WS_CLI = 4, WS_COUNT = 5 };
 
 struct los_ctx {
   int device = 0;
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};
+  // multipole list whose sample tables are in WS_LSEL ({lmin, lmax, ls...})
+  std::vector<int32_t> lsel_key;
+  // multipole list whose knots (as doubles) are in WS_CLI
+  std::vector<int32_t> cli_key;
 };
 
 namespace {
@@ -290,6 +295,97 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
                              delta, stream);
 }
 
+int los_project_lsample(los_ctx *ctx, int32_t lmin, int32_t lmax, const int32_t *ls,
+                        int32_t nls, int64_t nk, int64_t ntau, double tau0, const double *k,
+                        const double *tau, const double *w_tau, const double *S, int32_t nsrc,
+                        uint32_t kernel_mask, double *delta, void *stream) {
+  if (!ctx) return fail(LOS_ERR_INVALID, "los_project_lsample: ctx is NULL");
+  if (lmin < 2 || lmax < lmin || lmax > 16000)
+    return fail(LOS_ERR_INVALID, "los_project_lsample: need 2 <= lmin <= lmax <= 16000");
+  if (!ls || nls < 1 || nls > lmax - lmin + 1)
+    return fail(LOS_ERR_INVALID, "los_project_lsample: need 1 <= nls <= lmax - lmin + 1 and ls");
+  for (int32_t i = 0; i < nls; ++i) {
+    if (ls[i] < lmin || ls[i] > lmax || (i > 0 && ls[i] <= ls[i - 1]))
+      return fail(LOS_ERR_INVALID,
+                  "los_project_lsample: ls must increase strictly within [lmin, lmax] (ls[%d] = %d)",
+                  i, ls[i]);
+  }
+  if (nk < 1 || nk > ((int64_t)1 << 31) - 1)
+    return fail(LOS_ERR_INVALID, "los_project_lsample: nk = %lld out of range", (long long)nk);
+  if (ntau < 1 || ntau > 8192)
+    return fail(LOS_ERR_INVALID, "los_project_lsample: ntau = %lld out of [1, 8192]",
+                (long long)ntau);
+  if (nsrc < 1 || nsrc > 4)
+    return fail(LOS_ERR_INVALID, "los_project_lsample: nsrc = %d out of [1, 4]", nsrc);
+  if (!(tau0 == tau0)) return fail(LOS_ERR_INVALID, "los_project_lsample: tau0 is NaN");
+  if (!k || !tau || !w_tau || !S || !delta)
+    return fail(LOS_ERR_INVALID, "los_project_lsample: NULL array");
+  if (nsrc < 32 && (kernel_mask >> nsrc) != 0)
+    return fail(LOS_ERR_INVALID, "los_project_lsample: kernel mask 0x%x names a source >= nsrc",
+                kernel_mask);
+  const char *scheme = std::getenv("LOS_PROJ_SCHEME");
+  if (scheme && std::atoi(scheme) == 0)
+    return fail(LOS_ERR_UNSUPPORTED, "los_project_lsample: needs the sweep scheme");
+  los::ProjectShape sh = los::project_fp64_desc_shape(
+      nsrc, ntau, env_int("LOS_PROJ_WAVES"), env_int("LOS_PROJ_SLOTS"), 16,
+      (size_t)std::max(0, env_int("LOS_PROJ_LDS_EXTRA")));
+  if (sh.waves == 0 || sh.lds > 160 * 1024)
+    return fail(LOS_ERR_UNSUPPORTED, "los_project_lsample: no launch shape for ntau = %lld",
+                (long long)ntau);
+  // device tables (output row per multipole, sampled-row mask per 16-row
+  // block), rebuilt only when the list changes
+  const int nl = lmax - lmin + 1, nblk = (nl + 15) / 16;
+  const size_t bytes = sizeof(int32_t) * (size_t)nl + sizeof(uint32_t) * (size_t)nblk;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int32_t> key;
+  key.reserve((size_t)nls + 2);
+  key.push_back(lmin);
+  key.push_back(lmax);
+  key.insert(key.end(), ls, ls + nls);
+  void *ws = ctx->ws[WS_LSEL];
+  if (key != ctx->lsel_key || ctx->ws_bytes[WS_LSEL] < bytes) {
+    std::vector<int32_t> lsel((size_t)nl, -1);
+    std::vector<uint32_t> bmask((size_t)nblk, 0u);
+    for (int32_t i = 0; i < nls; ++i) {
+      const int r = ls[i] - lmin;
+      lsel[(size_t)r] = i;
+      bmask[(size_t)(r / 16)] |= 1u << (r % 16);
+    }
+    // the previous tables may still be read by queued work on this stream
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "los_project_lsample: stream");
+    ctx->lsel_key.clear();
+    int rc = ws_reserve(ctx, WS_LSEL, bytes, &ws);
+    if (rc != LOS_OK) return rc;
+    e = hipMemcpy(ws, lsel.data(), sizeof(int32_t) * (size_t)nl, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy((char *)ws + sizeof(int32_t) * (size_t)nl, bmask.data(),
+                    sizeof(uint32_t) * (size_t)nblk, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "los_project_lsample: copying the sample tables");
+    ctx->lsel_key.swap(key);
+  }
+  los::ProjectArgs a{};
+  a.lmin = lmin;
+  a.lmax = lmax;
+  a.nl = nl;
+  a.nblk = (nl + los::kProjectBlock - 1) / los::kProjectBlock;
+  a.nk = nk;
+  a.ntau = ntau;
+  a.tau0 = tau0;
+  a.k = k;
+  a.tau = tau;
+  a.w = w_tau;
+  a.S = S;
+  a.delta = delta;
+  a.emask = kernel_mask;
+  a.lsel = (const int32_t *)ws;
+  a.bmask = (const uint32_t *)((const char *)ws + sizeof(int32_t) * (size_t)nl);
+  a.nls = nls;
+  hipError_t e = los::project_fp64_desc_launch(a, nsrc, sh, st);
+  if (e != hipSuccess) return hip_fail(e, "los_project_lsample launch");
+  return ok();
+}
+
 int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc, int32_t nl,
                  int64_t nk, const double *w_lnk, const double *Pk, const int32_t *pairs,
                  int32_t npairs, double *cl, void *stream) {
@@ -386,6 +482,50 @@ int los_interp_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, co
   hipError_t e = los::spline_eval_launch(q, nkc, Sc, M, k, nk, nsrc, ntau, out_prec, S,
                                          (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "los_interp_sources launch");
+  return ok();
+}
+
+int los_cl_interp(los_ctx *ctx, int32_t npairs, const int32_t *ls, int32_t nls,
+                  const double *cls, int32_t lmin, int32_t lmax, double *cl, void *stream) {
+  if (!ctx) return fail(LOS_ERR_INVALID, "los_cl_interp: ctx is NULL");
+  if (npairs < 1 || npairs > 65535)
+    return fail(LOS_ERR_INVALID, "los_cl_interp: npairs = %d out of [1, 65535]", npairs);
+  if (!ls || nls < 1 || nls > 2048)
+    return fail(LOS_ERR_INVALID, "los_cl_interp: need 1 <= nls <= 2048 and ls");
+  if (lmin < 2 || lmax < lmin || ls[0] != lmin || ls[nls - 1] != lmax)
+    return fail(LOS_ERR_INVALID,
+                "los_cl_interp: need 2 <= lmin <= lmax with ls[0] = lmin and ls[nls-1] = lmax");
+  for (int32_t i = 1; i < nls; ++i)
+    if (ls[i] <= ls[i - 1])
+      return fail(LOS_ERR_INVALID, "los_cl_interp: ls must increase strictly (ls[%d] = %d)", i,
+                  ls[i]);
+  if (!cls || !cl) return fail(LOS_ERR_INVALID, "los_cl_interp: NULL array");
+  if ((const void *)cls == (const void *)cl)
+    return fail(LOS_ERR_INVALID, "los_cl_interp: cl must not alias cls");
+  hipStream_t st = (hipStream_t)stream;
+  if (nls == 1) {  // lmin == lmax: the single value
+    hipError_t e = hipMemcpyAsync(cl, cls, sizeof(double) * (size_t)npairs,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "los_cl_interp copy");
+    return ok();
+  }
+  std::vector<int32_t> key(ls, ls + nls);
+  void *ws = ctx->ws[WS_CLI];
+  if (key != ctx->cli_key || ctx->ws_bytes[WS_CLI] < sizeof(double) * (size_t)nls) {
+    std::vector<double> knots((size_t)nls);
+    for (int32_t i = 0; i < nls; ++i) knots[(size_t)i] = (double)ls[i];
+    // the previous knots may still be read by queued work on this stream
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "los_cl_interp: stream");
+    ctx->cli_key.clear();
+    int rc = ws_reserve(ctx, WS_CLI, sizeof(double) * (size_t)nls, &ws);
+    if (rc != LOS_OK) return rc;
+    e = hipMemcpy(ws, knots.data(), sizeof(double) * (size_t)nls, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "los_cl_interp: copying the knots");
+    ctx->cli_key.swap(key);
+  }
+  hipError_t e = los::cl_interp_launch((const double *)ws, nls, cls, npairs, lmin, lmax, cl, st);
+  if (e != hipSuccess) return hip_fail(e, "los_cl_interp launch");
   return ok();
 }
 

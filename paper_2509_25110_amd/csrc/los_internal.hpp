@@ -19,6 +19,13 @@ struct ProjectArgs {
   const double *S;  // [nsrc][nk][ntau]
   double *delta;    // [nk][nl][nsrc]
   uint32_t emask;   // bit s: source s uses the E-mode kernel eps_l (sweep kernel only)
+  // Multipole sampling (sweep kernel, 16-row blocks): when lsel is set, only
+  // rows l with lsel[l - lmin] >= 0 are accumulated and stored, at output
+  // row lsel[l - lmin] of delta[k][nls][nsrc]; bmask[bi] has bit r set when
+  // row lmin + 16 bi + r is sampled.
+  const int32_t *lsel = nullptr;
+  const uint32_t *bmask = nullptr;
+  int nls = 0;
 };
 
 // Launch shape chosen by the host for the FP64 projection.
@@ -137,6 +144,11 @@ struct ClArgs {
 };
 int cl_segments(int64_t nk, int nl);
 hipError_t cl_launch(const ClArgs &a, hipStream_t s);
+
+// C_l at every l from sampled multipoles: natural spline of l (l+1) C_l
+// (cl_interp.hip); knots[nls] (doubles) in device memory, 2 <= nls <= 2048.
+hipError_t cl_interp_launch(const double *knots, int nls, const double *cls, int npairs, int lmin,
+                            int lmax, double *cl, hipStream_t s);
 
 // Natural cubic spline of the sources in k (spline.hip).  The tables depend
 // on the knots only: per interior row (P * 16 rows, padded) the local Thomas

@@ -44,9 +44,10 @@ using fp64::wave_reduce;
 
 // One slot over the block of rows top .. top-B+1, descending.  (p1, p0) =
 // (w j_{l+1}, w j_l) at l = top on entry, at l = top - B on return.
-template <int NSRC, int B>
+template <int NSRC, int B, bool SMP>
 __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, double &p0,
-                                           double ix, const double (&sv)[NSRC], int top) {
+                                           double ix, const double (&sv)[NSRC], int top,
+                                           uint32_t sm) {
   double t = 0.0;
   const double d2 = ix + ix;
 #pragma unroll
@@ -55,8 +56,10 @@ __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, 
     // -2/x in between (at most 7 rounding steps, whatever the block size)
     if (i % 8 == 0) t = (double)(2 * (top - i) + 1) * ix;
     const int q = (B - 1 - i) * NSRC;
+    if (!SMP || ((sm >> (B - 1 - i)) & 1u)) {  // uniform: row top - i is sampled
 #pragma unroll
-    for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
+      for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
+    }
     const double nx = rec_step(t, p0, p1);
     p1 = p0;
     p0 = nx;
@@ -64,7 +67,7 @@ __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, 
   }
 }
 
-template <int NSRC, int T, int B>
+template <int NSRC, int T, int B, bool SMP>
 __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   constexpr int NV = B * NSRC;
   const int nblk = (a.nl + B - 1) / B;
@@ -182,12 +185,20 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
     }
   }
 
-  double *drow = a.delta + ki * (int64_t)a.nl * NSRC;
+  double *drow = a.delta + ki * (int64_t)(SMP ? a.nls : a.nl) * NSRC;
+  // output offset of row l = b + lane / NSRC, source lane % NSRC (-1: not stored)
+  auto out_at = [&](int b) -> int64_t {
+    const int l = b + lane / NSRC;
+    if (l > lmax) return -1;
+    if (!SMP) return (int64_t)(b - lmin) * NSRC + lane;
+    const int r = a.lsel[l - lmin];
+    return r < 0 ? -1 : (int64_t)r * NSRC + lane % NSRC;
+  };
   // blocks above every lane's top row are zero
   if (w == 0 && lane < NV) {
     for (int bi = top_blk + 1; bi < nblk; ++bi) {
-      const int b = lmin + bi * B;
-      if (b + lane / NSRC <= lmax) drow[(int64_t)(b - lmin) * NSRC + lane] = 0.0;
+      const int64_t o = out_at(lmin + bi * B);
+      if (o >= 0) drow[o] = 0.0;
     }
   }
   // with E-mode limit terms, block 0 is swept even when no node reaches it
@@ -209,6 +220,7 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
     const uint64_t fm = slot_mask(thF >= bi);        // all lanes live through the block
     const uint64_t pm = slot_mask(thA >= bi) & ~fm;  // some lanes start inside it
     const uint64_t fmn = bi > 0 ? slot_mask(thF >= bi - 1) : 0;  // the next block's
+    const uint32_t sm = SMP ? a.bmask[bi] : 0u;  // sampled rows of this block (bit r: row b + r)
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
@@ -232,7 +244,7 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         for (int s = 0; s < NSRC; ++s)
           if ((a.emask >> s) & 1u) sv[s] *= i2;
       }
-      sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ix, sv, top);
+      sweep_slot<NSRC, B, SMP>(acc, Jn[j], Jc[j], ix, sv, top, sm);
     }
 #pragma unroll
     for (int j = 0; j < T; ++j) {
@@ -250,7 +262,7 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
             if ((a.emask >> s) & 1u) sv[s] *= i2;
         }
         if (rs[n] >= top)  // this lane is live through the block (R is a block top)
-          sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ixs[n], sv, top);
+          sweep_slot<NSRC, B, SMP>(acc, Jn[j], Jc[j], ixs[n], sv, top, sm);
       }
     }
     if (bi == 0) {  // row l = lmin: the x -> 0 E-mode terms (zero unless emask and lmin = 2)
@@ -261,28 +273,34 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
     // (bi % 4 == 0) the workgroup synchronises once and wave 0 sums the waves
     // in a fixed order and stores those blocks, while the other waves go on
     // into the other half of the ring.
-    const double part = wave_reduce<NV>(acc, stage, lane);
-    if (lane < NV) cross[((bi & 7) * W + w) * NV + lane] = part;
+    // With multipole sampling, blocks holding no sampled row skip all of this
+    // except the (uniform) barrier.
+    if (!SMP || sm != 0u) {
+      const double part = wave_reduce<NV>(acc, stage, lane);
+      if (lane < NV) cross[((bi & 7) * W + w) * NV + lane] = part;
+    }
     if ((bi & 3) == 0) {
       __syncthreads();
       if (w == 0 && lane < NV) {
         const int hi = bi + 3 < first ? bi + 3 : first;
         for (int bb = hi; bb >= bi; --bb) {
+          if (SMP && a.bmask[bb] == 0u) continue;
           double tot = 0.0;
           for (int ww = 0; ww < W; ++ww) tot += cross[((bb & 7) * W + ww) * NV + lane];
           const int l = lmin + bb * B + lane / NSRC;
           if ((a.emask >> (lane % NSRC)) & 1u)
             tot *= sqrt((double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2));
-          if (l <= lmax) drow[(int64_t)(bb * B) * NSRC + lane] = tot;
+          const int64_t o = out_at(lmin + bb * B);
+          if (o >= 0) drow[o] = tot;
         }
       }
     }
   }
 }
 
-template <int NSRC, int T, int B>
+template <int NSRC, int T, int B, bool SMP>
 hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
-  auto kern = project_fp64_desc_kernel<NSRC, T, B>;
+  auto kern = project_fp64_desc_kernel<NSRC, T, B, SMP>;
   if (sh.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
@@ -292,20 +310,24 @@ hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s)
   return hipGetLastError();
 }
 
-template <int NSRC, int B>
+template <int NSRC, int B, bool SMP>
 hipError_t launch_b(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
   switch (sh.slots) {
-    case 4: return launch_t<NSRC, 4, B>(a, sh, s);
-    case 8: return launch_t<NSRC, 8, B>(a, sh, s);
-    case 12: return launch_t<NSRC, 12, B>(a, sh, s);
-    case 16: return launch_t<NSRC, 16, B>(a, sh, s);
+    case 4: return launch_t<NSRC, 4, B, SMP>(a, sh, s);
+    case 8: return launch_t<NSRC, 8, B, SMP>(a, sh, s);
+    case 12: return launch_t<NSRC, 12, B, SMP>(a, sh, s);
+    case 16: return launch_t<NSRC, 16, B, SMP>(a, sh, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int NSRC>
 hipError_t launch_n(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
-  return sh.block == 16 ? launch_b<NSRC, 16>(a, sh, s) : launch_b<NSRC, 8>(a, sh, s);
+  if (a.lsel) {  // multipole sampling: 16-row blocks only
+    if (sh.block != 16 || !a.bmask) return hipErrorInvalidValue;
+    return launch_b<NSRC, 16, true>(a, sh, s);
+  }
+  return sh.block == 16 ? launch_b<NSRC, 16, false>(a, sh, s) : launch_b<NSRC, 8, false>(a, sh, s);
 }
 
 }  // namespace

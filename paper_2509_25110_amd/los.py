@@ -34,7 +34,8 @@ _STATUS = {1: "LOS_ERR_INVALID", 2: "LOS_ERR_HIP", 3: "LOS_ERR_OOM", 4: "LOS_ERR
 # every symbol include/los.h declares
 EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
            "los_bessel_table", "los_project", "los_project_kernels", "cl_integrate",
-           "los_spline_sources", "los_interp_sources", "los_batch_create",
+           "los_spline_sources", "los_interp_sources", "los_project_lsample", "los_cl_interp",
+           "los_batch_create",
            "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_destroy",
            "emu_create", "emu_destroy", "emu_nparams", "emu_get_params", "emu_set_params",
            "emu_get_pca", "emu_set_pca", "emu_forward", "emu_loss_grad", "emu_fit", "emu_train",
@@ -71,6 +72,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cl_integrate.restype = ctypes.c_int
     lib.cl_integrate.argtypes = [vp, vp, i32, i32, i32, i64, vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
+    lib.los_project_lsample.restype = ctypes.c_int
+    lib.los_project_lsample.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int32), i32, i64,
+                                        i64, dbl, vp, vp, vp, vp, i32, ctypes.c_uint32, vp, vp]
+    lib.los_cl_interp.restype = ctypes.c_int
+    lib.los_cl_interp.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), i32, vp, i32, i32, vp,
+                                  vp]
     lib.los_spline_sources.restype = ctypes.c_int
     lib.los_spline_sources.argtypes = [vp, i32, i64, i64, vp, vp, vp, vp]
     lib.los_interp_sources.restype = ctypes.c_int
@@ -237,6 +244,40 @@ class Context:
                                   arr, npairs, _ptr(cl), _stream(stream)))
         return cl
 
+
+    def los_project_lsample(self, lmin: int, lmax: int, ls, k: torch.Tensor, tau: torch.Tensor,
+                            tau0: float, w_tau: torch.Tensor, S: torch.Tensor, kernel_mask: int = 0,
+                            delta: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """FP64 projection at the sampled multipoles ls (host list): delta[nk, len(ls), nsrc]."""
+        nsrc, nk, ntau = S.shape
+        lsl = [int(v) for v in ls]
+        arr = (ctypes.c_int32 * len(lsl))(*lsl)
+        if delta is None:
+            delta = torch.empty((nk, len(lsl), nsrc), dtype=torch.float64, device=S.device)
+        _need(S, torch.float64, nsrc * nk * ntau, "S")
+        _need(k, torch.float64, nk, "k")
+        _need(tau, torch.float64, ntau, "tau")
+        _need(w_tau, torch.float64, ntau, "w_tau")
+        _need(delta, torch.float64, nk * len(lsl) * nsrc, "delta")
+        _check(lib().los_project_lsample(self._h, lmin, lmax, arr, len(lsl), nk, ntau, float(tau0),
+                                         _ptr(k), _ptr(tau), _ptr(w_tau), _ptr(S), nsrc,
+                                         int(kernel_mask), _ptr(delta), _stream(stream)))
+        return delta
+
+    def los_cl_interp(self, ls, cls: torch.Tensor, lmin: int, lmax: int,
+                      cl: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """C_l at every l in [lmin, lmax] from cls[npairs, len(ls)] at the sampled ls."""
+        lsl = [int(v) for v in ls]
+        arr = (ctypes.c_int32 * len(lsl))(*lsl)
+        npairs = cls.numel() // max(len(lsl), 1)
+        nl = lmax - lmin + 1
+        if cl is None:
+            cl = torch.empty((npairs, nl), dtype=torch.float64, device=cls.device)
+        _need(cls, torch.float64, npairs * len(lsl), "cls")
+        _need(cl, torch.float64, npairs * nl, "cl")
+        _check(lib().los_cl_interp(self._h, npairs, arr, len(lsl), _ptr(cls), lmin, lmax, _ptr(cl),
+                                   _stream(stream)))
+        return cl
 
     def los_spline_sources(self, q: torch.Tensor, Sc: torch.Tensor,
                            M: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

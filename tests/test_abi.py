@@ -129,3 +129,23 @@ def test_spline_validation(lib):
     assert ip(ctx, 1, 10, 8, p, p, m, 4, p, 0, m, None) == 1   # S aliases M
     assert ip(ctx, 1, 10, 8, p, p, m, 0, None, 0, None, None) == 0  # nk == 0: no-op
     assert sp(None, 1, 10, 8, p, p, m, None) == 1
+
+
+def test_lsample_validation(lib):
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)
+    d = ctypes.c_void_p(64)
+    ls = (ctypes.c_int32 * 3)(2, 5, 9)
+    f = lib.los_project_lsample
+    bad = (ctypes.c_int32 * 3)(2, 5, 5)
+    assert f(ctx, 2, 9, bad, 3, 4, 8, 1.0, p, p, p, p, 1, 0, d, None) == 1       # not increasing
+    out = (ctypes.c_int32 * 2)(2, 12)
+    assert f(ctx, 2, 9, out, 2, 4, 8, 1.0, p, p, p, p, 1, 0, d, None) == 1       # beyond lmax
+    assert f(ctx, 2, 9, ls, 0, 4, 8, 1.0, p, p, p, p, 1, 0, d, None) == 1        # nls = 0
+    assert f(ctx, 2, 9, ls, 3, 4, 8, 1.0, p, p, p, p, 1, 0b10, d, None) == 1     # mask bit >= nsrc
+    ci = lib.los_cl_interp
+    assert ci(ctx, 2, ls, 3, p, 2, 10, d, None) == 1      # last sample != lmax
+    assert ci(ctx, 2, ls, 3, p, 3, 9, d, None) == 1       # first sample != lmin
+    assert ci(ctx, 2, ls, 3, p, 2, 9, p, None) == 1       # cl aliases cls
+    assert ci(ctx, 0, ls, 3, p, 2, 9, d, None) == 1       # npairs = 0
+    assert ci(None, 2, ls, 3, p, 2, 9, d, None) == 1
