@@ -44,10 +44,9 @@ using fp64::wave_reduce;
 
 // One slot over the block of rows top .. top-B+1, descending.  (p1, p0) =
 // (w j_{l+1}, w j_l) at l = top on entry, at l = top - B on return.
-template <int NSRC, int B, bool SMP>
+template <int NSRC, int B>
 __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, double &p0,
-                                           double ix, const double (&sv)[NSRC], int top,
-                                           uint32_t sm) {
+                                           double ix, const double (&sv)[NSRC], int top) {
   double t = 0.0;
   const double d2 = ix + ix;
 #pragma unroll
@@ -56,10 +55,8 @@ __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, 
     // -2/x in between (at most 7 rounding steps, whatever the block size)
     if (i % 8 == 0) t = (double)(2 * (top - i) + 1) * ix;
     const int q = (B - 1 - i) * NSRC;
-    if (!SMP || ((sm >> (B - 1 - i)) & 1u)) {  // uniform: row top - i is sampled
 #pragma unroll
-      for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
-    }
+    for (int s = 0; s < NSRC; ++s) acc[q + s] = fma(p0, sv[s], acc[q + s]);
     const double nx = rec_step(t, p0, p1);
     p1 = p0;
     p0 = nx;
@@ -244,7 +241,7 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         for (int s = 0; s < NSRC; ++s)
           if ((a.emask >> s) & 1u) sv[s] *= i2;
       }
-      sweep_slot<NSRC, B, SMP>(acc, Jn[j], Jc[j], ix, sv, top, sm);
+      sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ix, sv, top);
     }
 #pragma unroll
     for (int j = 0; j < T; ++j) {
@@ -252,18 +249,17 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
       if (nb >= ntau) break;
       int n = nb + lane;
       asm volatile("" : "+v"(n));
-      if (has(pm, j)) {
-        double sv[NSRC];
-        load_s<NSRC>(sv, srow, n, ntau);
-        if (a.emask != 0) {  // uniform
-          const double i2 = ixs[n] * ixs[n];
+      if (!has(pm, j)) continue;
+      double sv[NSRC];
+      load_s<NSRC>(sv, srow, n, ntau);
+      if (a.emask != 0) {  // uniform
+        const double i2 = ixs[n] * ixs[n];
 #pragma unroll
-          for (int s = 0; s < NSRC; ++s)
-            if ((a.emask >> s) & 1u) sv[s] *= i2;
-        }
-        if (rs[n] >= top)  // this lane is live through the block (R is a block top)
-          sweep_slot<NSRC, B, SMP>(acc, Jn[j], Jc[j], ixs[n], sv, top, sm);
+        for (int s = 0; s < NSRC; ++s)
+          if ((a.emask >> s) & 1u) sv[s] *= i2;
       }
+      if (rs[n] >= top)  // this lane is live through the block (R is a block top)
+        sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ixs[n], sv, top);
     }
     if (bi == 0) {  // row l = lmin: the x -> 0 E-mode terms (zero unless emask and lmin = 2)
 #pragma unroll
