@@ -5,8 +5,9 @@
 // HBM-bound reduction over k.  Pass 1: a grid of (l tile of 64, k segment)
 // single-wave workgroups; lane = l, loop over the segment's k in order,
 // FP64 accumulators per pair; coalesced reads of delta[k][l0..l0+63][*].
-// Pass 2: one lane per (p, l) sums the segment partials in segment order and
-// applies 4 pi.  Fixed summation order -> bitwise reproducible.
+// Pass 2: one wave per (p, l) sums the segment partials (each lane a stride
+// of them, then a fixed butterfly) and applies 4 pi.  Fixed summation order
+// -> bitwise reproducible.
 #include "los_internal.hpp"
 
 namespace los {
@@ -51,12 +52,19 @@ __global__ void __launch_bounds__(64) cl_partial_kernel(ClArgs a) {
     if (p < a.npairs) a.partial[((int64_t)seg * a.npairs + p) * a.nl + l] = acc[p];
 }
 
+// One wave per output: lane i sums the partials of segments i, i + 64, ...
+// in increasing order, then the 64 lane sums are combined by a fixed
+// butterfly (xor 32, 16, ..., 1), so the result is the same on every run.
 __global__ void __launch_bounds__(256) cl_final_kernel(ClArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)a.npairs * a.nl) return;
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (t >= (int64_t)a.npairs * a.nl) return;  // whole wave: t is uniform
   double s = 0.0;
-  for (int seg = 0; seg < a.nseg; ++seg) s += a.partial[(int64_t)seg * a.npairs * a.nl + t];
-  a.cl[t] = 4.0 * 3.14159265358979323846 * s;
+  for (int seg = lane; seg < a.nseg; seg += 64)
+    s += a.partial[(int64_t)seg * a.npairs * a.nl + t];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) a.cl[t] = 4.0 * 3.14159265358979323846 * s;
 }
 
 template <typename DT>
@@ -71,8 +79,9 @@ hipError_t launch_dt(const ClArgs &a, hipStream_t st) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t n = (int64_t)a.npairs * a.nl;
-  hipLaunchKernelGGL(cl_final_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  const int64_t n = (int64_t)a.npairs * a.nl;  // one wave each, four waves per workgroup
+  if ((n + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cl_final_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
