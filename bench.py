@@ -457,8 +457,9 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the projection shards over k; see "
-              "DESIGN.md); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: only one GPU is measured (the projection would shard over k, with one "
+              "all-reduce of the partial C_l); --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     if args.config == "C4":
