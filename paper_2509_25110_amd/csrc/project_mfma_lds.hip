@@ -206,13 +206,18 @@ hipError_t mfma_gemm_lds_launch(const GemmArgs &a, int kcount, int max_ncol, hip
   const int64_t total = (int64_t)tiles_m * tiles_n * kcount;
   const int64_t grid = ((total + 7) / 8) * 8;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)mfma_gemm_lds_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)gemm_lds_bytes());
+  // the LDS limit is a per-device function attribute: set once per device
+  // (the batch first launches this kernel from its autotuner, outside capture)
+  static bool attr_set[256] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+  if (!attr_set[dev]) {
+    e = hipFuncSetAttribute((const void *)mfma_gemm_lds_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds_bytes());
     if (e != hipSuccess) return e;
-    attr = true;
+    attr_set[dev] = true;
   }
   hipLaunchKernelGGL(mfma_gemm_lds_kernel, dim3((unsigned)grid), dim3(512), gemm_lds_bytes(), s,
                      a, tiles_m, tiles_n, kcount);

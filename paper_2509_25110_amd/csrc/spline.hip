@@ -317,16 +317,14 @@ hipError_t spline_solve_launch(const double *q, const double *Sc, double *M, int
   if (P > kSplineMaxSegments) return hipErrorInvalidValue;
   if (ncols > 0x7fffffff) return hipErrorInvalidValue;
   const size_t flds = sizeof(double) * (4 + kRed) * (size_t)P;  // <= 80 KiB
-  static bool big_lds = false;
-  if (flds > 64 * 1024 && !big_lds) {
-    hipError_t e = hipFuncSetAttribute((const void *)spline_factor_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * (4 + kRed) * kSplineMaxSegments));
+  hipError_t e = hipSuccess;
+  if (flds > 64 * 1024) {  // a per-device function attribute: set on every such launch
+    e = hipFuncSetAttribute((const void *)spline_factor_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)flds);
     if (e != hipSuccess) return e;
-    big_lds = true;
   }
   hipLaunchKernelGGL(spline_factor_kernel, dim3(1), dim3(256), flds, s, q, N, (int)P, t);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int Pi = (int)P;
   // about 512 threads per workgroup, so that two share a CU and one's serial
