@@ -26,6 +26,9 @@ struct ProjectArgs {
   const int32_t *lsel = nullptr;
   const uint32_t *bmask = nullptr;
   int nls = 0;
+  // sweep kernel: blocks of partial sums kept in LDS (2 or 8; the workgroup
+  // synchronises every ring/2 blocks).  Set from ProjectShape::ring.
+  int ring = 8;
 };
 
 // Launch shape chosen by the host for the FP64 projection.
@@ -34,6 +37,7 @@ struct ProjectShape {
   int slots;      // tau slots per lane (4, 8, 12, 16)
   size_t lds;     // dynamic LDS bytes
   int block = 8;  // l rows per block (descending sweep: 8 or 16)
+  int ring = 8;   // descending sweep: blocks of partials in LDS (2 or 8)
 };
 
 // FP64 projection: one workgroup per k.

@@ -81,8 +81,9 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   int *rs = (int *)(lds + npad);                      // [npad] top row R per node (-1: none)
   double *const lds2 = lds + npad + (npad + 1) / 2;
   double *stage = lds2 + w * fp64::stage_doubles(NV);                 // per wave [16][NV+1]
-  double *cross = lds2 + W * fp64::stage_doubles(NV);  // [8][W][NV] ring of block partials
-  int *bnd = (int *)(cross + 8 * W * NV);              // [1]
+  const int nring = a.ring, half = nring >> 1;         // 8 or 2 blocks of partials
+  double *cross = lds2 + W * fp64::stage_doubles(NV);  // [nring][W][NV] block partials
+  int *bnd = (int *)(cross + nring * W * NV);          // [1]
 
   const double kk = a.k[ki];
   const double *srow[NSRC];
@@ -265,24 +266,24 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
 #pragma unroll
       for (int s = 0; s < NSRC; ++s) acc[s] += e2[s];
     }
-    // Each wave leaves its block total in ring slot bi % 8; every 4 blocks
-    // (bi % 4 == 0) the workgroup synchronises once and wave 0 sums the waves
-    // in a fixed order and stores those blocks, while the other waves go on
-    // into the other half of the ring.
+    // Each wave leaves its block total in slot bi % nring; every nring/2
+    // blocks (bi % (nring/2) == 0) the workgroup synchronises once and wave 0
+    // sums the waves in a fixed order and stores those blocks, while the
+    // other waves go on into the other half of the ring.
     // With multipole sampling, blocks holding no sampled row skip all of this
     // except the (uniform) barrier.
     if (!SMP || sm != 0u) {
       const double part = wave_reduce<NV>(acc, stage, lane);
-      if (lane < NV) cross[((bi & 7) * W + w) * NV + lane] = part;
+      if (lane < NV) cross[((bi & (nring - 1)) * W + w) * NV + lane] = part;
     }
-    if ((bi & 3) == 0) {
+    if ((bi & (half - 1)) == 0) {
       __syncthreads();
       if (w == 0 && lane < NV) {
-        const int hi = bi + 3 < first ? bi + 3 : first;
+        const int hi = bi + half - 1 < first ? bi + half - 1 : first;
         for (int bb = hi; bb >= bi; --bb) {
           if (SMP && a.bmask[bb] == 0u) continue;
           double tot = 0.0;
-          for (int ww = 0; ww < W; ++ww) tot += cross[((bb & 7) * W + ww) * NV + lane];
+          for (int ww = 0; ww < W; ++ww) tot += cross[((bb & (nring - 1)) * W + ww) * NV + lane];
           const int l = lmin + bb * B + lane / NSRC;
           if ((a.emask >> (lane % NSRC)) & 1u)
             tot *= sqrt((double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2));
@@ -302,7 +303,9 @@ hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s)
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)a.nk), dim3(64 * sh.waves), sh.lds, s, a);
+  ProjectArgs b = a;
+  b.ring = sh.ring;
+  hipLaunchKernelGGL(kern, dim3((unsigned)b.nk), dim3(64 * sh.waves), sh.lds, s, b);
   return hipGetLastError();
 }
 
@@ -328,24 +331,54 @@ hipError_t launch_n(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s)
 
 }  // namespace
 
+static size_t desc_lds_bytes(int W, int T, int NV, int ring, size_t lds_extra) {
+  const size_t npad = (size_t)W * 64 * T;
+  return sizeof(double) * (npad + (npad + 1) / 2 + (size_t)W * fp64::stage_doubles(NV) +
+                           (size_t)ring * W * NV) +
+         4 * sizeof(int) + lds_extra;
+}
+
+// Launch shape: W waves per workgroup, T slots per lane (T a multiple of 4,
+// 64 W T >= ntau) and the ring of block partials (8, else 2 where 8 does not
+// fit).  The kernel needs more than 128 VGPRs for every T, so a SIMD holds at
+// most 2 of its waves (8 per CU); LDS (160 KiB per CU) may allow fewer.
+// Chosen: the most resident waves per CU, then the least padding (idle
+// lanes), then fewer waves per workgroup (less reduction work), then the
+// larger ring (fewer barriers).
 ProjectShape project_fp64_desc_shape(int nsrc, int64_t ntau, int force_waves, int force_slots,
                                      int block, size_t lds_extra) {
   ProjectShape sh{};
   sh.block = block == 8 ? 8 : 16;  // 16 rows per reduction halves the source reloads
-  int W = force_waves > 0 ? force_waves : (int)((ntau + 64 * 12 - 1) / (64 * 12));
-  if (W < 1) W = 1;
-  if (W > 8) return sh;
-  int T = force_slots > 0 ? force_slots : (int)((ntau + 64 * W - 1) / (64 * W));
-  T = (T + 3) / 4 * 4;
-  if (T < 4) T = 4;
-  if (T > 16 || (int64_t)64 * W * T < ntau) return sh;  // waves == 0: unsupported
-  sh.waves = W;
-  sh.slots = T;
   const int NV = sh.block * nsrc;
-  const int npad = W * 64 * T;
-  sh.lds = sizeof(double) * ((size_t)npad + (size_t)(npad + 1) / 2 + (size_t)W * fp64::stage_doubles(NV) +
-                            8 * (size_t)W * NV) +
-           4 * sizeof(int) + lds_extra;
+  constexpr size_t kLdsPerCu = 160 * 1024;
+  int bestW = 0, bestT = 0, bestR = 0, best_res = -1;
+  double best_eff = -1.0;
+  for (int W = 1; W <= 8; ++W) {
+    if (force_waves > 0 && W != force_waves) continue;
+    for (int T = 4; T <= 16; T += 4) {
+      if (force_slots > 0 && T != (force_slots + 3) / 4 * 4) continue;
+      if ((int64_t)64 * W * T < ntau) continue;
+      for (int ring = 8; ring >= 2; ring -= 6) {
+        const size_t lds = desc_lds_bytes(W, T, NV, ring, lds_extra);
+        if (lds > kLdsPerCu) continue;
+        const int fit = (int)(kLdsPerCu / lds);
+        const int res = (fit < 8 / W ? fit : 8 / W) * W;
+        const double eff = (double)ntau / (64.0 * W * T);
+        if (res > best_res || (res == best_res && eff > best_eff + 1e-9)) {
+          bestW = W;
+          bestT = T;
+          bestR = ring;
+          best_res = res;
+          best_eff = eff;
+        }
+      }
+    }
+  }
+  if (bestW == 0) return sh;  // waves == 0: unsupported
+  sh.waves = bestW;
+  sh.slots = bestT;
+  sh.ring = bestR;
+  sh.lds = desc_lds_bytes(bestW, bestT, NV, bestR, lds_extra);
   return sh;
 }
 
