@@ -61,6 +61,32 @@ __device__ inline void run_up(double &p, double &q, int l0, int l1, double ix) {
   }
 }
 
+// Two upward runs from l = 0, interleaved chunk by chunk (two independent
+// chains in flight), for as many whole chunks of 8 as fit below l1; returns
+// the l reached, from which each run goes on with run_up (the coefficient
+// cadence, and so every rounding, is that of run_up from 0).
+__device__ inline int run_up2(double &pa, double &qa, double &pb, double &qb, int l1, double ixa,
+                              double ixb) {
+  const double da = ixa + ixa, db = ixb + ixb;
+  int l = 0;
+  for (; l + 8 <= l1; l += 8) {
+    const double c = (double)(2 * l + 1);
+    double ta = c * ixa, tb = c * ixb;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double ra = rec_step(ta, qa, pa);
+      const double rb = rec_step(tb, qb, pb);
+      ta += da;
+      tb += db;
+      pa = qa;
+      qa = ra;
+      pb = qb;
+      qb = rb;
+    }
+  }
+  return l;
+}
+
 // Downward run from (hn, hc) = (f_{l0+1}, f_{l0}) to l1 <= l0: on return
 // (hn, hc) = (f_{l1+1}, f_{l1}).  Coefficients as in run_up, stepped by -2/x.
 __device__ inline void run_down(double &hn, double &hc, int l0, int l1, double ix) {

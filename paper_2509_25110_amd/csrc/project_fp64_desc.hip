@@ -100,55 +100,44 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   // Per-slot block thresholds held by lane j for slot j (wave-uniform):
   // the slot runs unmasked in blocks bi <= thF and at all in blocks bi <= thA.
   int thF = -1, thA = -1, my_top = -1;
-#pragma unroll
-  for (int j = 0; j < T; ++j) {
+  // Setup of slot j once its upward run has reached l = up (x, w, (p, q) =
+  // w (j_{up-1}, j_up)): the Miller part where needed, the pair at R, the
+  // per-node LDS entries and the slot's thresholds.
+  auto finish = [&](int j, bool live, double x, double ix, double p, double q) {
     const int n = (w + W * j) * 64 + lane;
     int R = -1;
-    double ix = 0.0, cur = 0.0, nxt = 0.0;
-    if (n < ntau) {
-      const double x = kk * (a.tau0 - a.tau[n]);
-      const double wn = a.w[n];
-      if (x >= kXTiny && wn != 0.0) {
-        ix = 1.0 / x;
-        double sn, cs;
-        sincos(x, &sn, &cs);
-        double p = wn * (cs * ix), q = wn * (sn * ix);  // w j_{-1}, w j_0
-        const double fx = floor(x);
-        if (fx >= (double)(lmax + 1)) {
-          // upward to the top row of the block holding lmax (at most B - 1
-          // rows past it; those rows are swept but never stored)
-          R = top_all;
-          run_up(p, q, 0, R + 1, ix);
-          cur = p;  // w j_R
-          nxt = q;  // w j_{R+1}
-        } else {
-          const int m = (int)fx;
-          run_up(p, q, 0, m, ix);
-          const double jm = q;  // w j_m
-          const int L0 = ltop_of(x);
-          const int Rc = L0 < lmax ? L0 : lmax;  // last row kept (band edge or lmax)
-          if (Rc >= lmin) {
-            // top row of the block holding Rc; Miller starts at or above it
-            R = lmin + (Rc - lmin) / B * B + (B - 1);
-            const int Ls = L0 > R ? L0 : R;
-            double hn = 0.0, hc = 1.0;  // Miller seeds (0, 1) at Ls
-            run_down(hn, hc, Ls, R, ix);
-            const double hR = hc, hR1 = hn;
-            run_down(hn, hc, R, m, ix);
-            const double sc = jm / hc;
-            cur = sc * hR;
-            nxt = sc * hR1;
-          }
+    double cur = 0.0, nxt = 0.0;
+    if (live) {
+      if (floor(x) >= (double)(lmax + 1)) {
+        R = top_all;
+        cur = p;  // w j_R
+        nxt = q;  // w j_{R+1}
+      } else {
+        const int m = (int)floor(x);
+        const double jm = q;  // w j_m
+        const int L0 = ltop_of(x);
+        const int Rc = L0 < lmax ? L0 : lmax;  // last row kept (band edge or lmax)
+        if (Rc >= lmin) {
+          // top row of the block holding Rc; Miller starts at or above it
+          R = lmin + (Rc - lmin) / B * B + (B - 1);
+          const int Ls = L0 > R ? L0 : R;
+          double hn = 0.0, hc = 1.0;  // Miller seeds (0, 1) at Ls
+          run_down(hn, hc, Ls, R, ix);
+          const double hR = hc, hR1 = hn;
+          run_down(hn, hc, R, m, ix);
+          const double sc = jm / hc;
+          cur = sc * hR;
+          nxt = sc * hR1;
         }
       }
     }
-    ixs[n] = ix;
+    ixs[n] = live ? ix : 0.0;
     rs[n] = R;
     Jc[j] = cur;
     Jn[j] = nxt;
     // wave-uniform thresholds of this slot
     const int rmax = wave_max(R), rmin = wave_min(R >= 0 ? R : -1);
-    // unmasked in block bi when every lane's R >= top of the block = lmin + 8 bi + 7
+    // unmasked in block bi when every lane's R >= top of the block
     const int f = rmin - lmin - (B - 1) >= 0 ? (rmin - lmin - (B - 1)) / B : -1;
     const int ab = rmax >= lmin ? (rmax - lmin) / B : -1;
     if (lane == j) {
@@ -156,6 +145,47 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
       thA = ab;
     }
     my_top = ab > my_top ? ab : my_top;
+  };
+  // Slots go in pairs: the two upward runs share their common length, two
+  // independent recurrence chains in flight; each then finishes on its own.
+#pragma unroll
+  for (int j = 0; j < T; j += 2) {
+    bool live[2];
+    double xs[2], ixv[2], pv[2], qv[2];
+    int up[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = (w + W * (j + h)) * 64 + lane;
+      live[h] = false;
+      xs[h] = 0.0;
+      ixv[h] = 0.0;
+      pv[h] = 0.0;
+      qv[h] = 0.0;
+      up[h] = 0;
+      if (n < ntau) {
+        const double x = kk * (a.tau0 - a.tau[n]);
+        const double wn = a.w[n];
+        if (x >= kXTiny && wn != 0.0) {
+          live[h] = true;
+          xs[h] = x;
+          ixv[h] = 1.0 / x;
+          double sn, cs;
+          sincos(x, &sn, &cs);
+          pv[h] = wn * (cs * ixv[h]);  // w j_{-1}
+          qv[h] = wn * (sn * ixv[h]);  // w j_0
+          // upward to the top row's successor (x >= lmax + 1) or to floor(x)
+          const double fx = floor(x);
+          up[h] = fx >= (double)(lmax + 1) ? top_all + 1 : (int)fx;
+        }
+      }
+    }
+    const int common = up[0] < up[1] ? up[0] : up[1];
+    const int l = run_up2(pv[0], qv[0], pv[1], qv[1], common, ixv[0], ixv[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      run_up(pv[h], qv[h], l, up[h], ixv[h]);
+      finish(j + h, live[h], xs[h], ixv[h], pv[h], qv[h]);
+    }
   }
   if (threadIdx.x == 0) bnd[0] = -1;
   __syncthreads();
