@@ -161,20 +161,29 @@ def golden_error_c4(cl, b):
     return worst
 
 
-def run_batch(args):
-    """C4: 256 drawn models on the shared 8000-point master k grid, one graph launch per step."""
-    import torch
-    from paper_2509_25110_amd import inputs, los
-    torch.cuda.set_device(0)
-    prec = PRECS[args.prec if args.prec != "fp64" else "bf16x3"]
-    b = inputs.batch_inputs(inputs.draw_models(256))
-    ctx = los.Context()
-    plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
-                                prec=prec)
-    col, ncols = plan.los_batch_columns()
-    S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
-    inputs.batch_sources_device(b, col, S, torch)
-    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+def batch_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter profile of the
+    same kernel source (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    plain device copy of known size); None when there is none or the source has changed."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s.txt" % (kernel.replace("_kernel", ""), workload))
+    src = os.path.join(ROOT, "paper_2509_25110_amd", "csrc", "project_fused.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#")):
+            key, val = line.split(":", 1)
+            fields[key.strip()] = val.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def batch_run_prec(plan, b, S, dv, prec_name, steps, warmup, torch):
+    """Time one precision of the C4 batch: K graph replays bracketed by HIP events (the step
+    time and `value`), then instrumented eager solves for the per-kernel device times."""
     km, tau, w, wk, Pk = dv(b.k_master), dv(b.tau), dv(b.w_tau), dv(b.w_lnk), dv(b.Pk)
     cl = torch.empty((b.nmodels, 4, int(b.lmax.max()) - 1), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -187,53 +196,141 @@ def run_batch(args):
     step()
     torch.cuda.synchronize()
     first_ms = (time.perf_counter() - t0) * 1e3
-    for _ in range(max(args.warmup - 1, 0)):
+    for _ in range(max(warmup - 1, 0)):
         step()
     torch.cuda.synchronize()
-    K = args.steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(K)]
-    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
-    for i in range(K):
-        ev[i][0].record(stream)
+    start.record(stream)
+    for _ in range(steps):
         step()
-        ev[i][1].record(stream)
+    end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    times = [a.elapsed_time(c) for a, c in ev]
-    ms = float(np.sum(times)) / K
-    err = golden_error_c4(cl.cpu().numpy(), b)
-    tp, dense = batch_tp_counts(b)
-    flops = 2.0 * 3 * tp
-    peak = PEAK["bf16x3_mfma" if prec == 2 else "fp32_mfma"]
-    achieved = flops / (ms * 1e-3) / 1e12
+    ms = start.elapsed_time(end) / steps
+    cl_host = cl.cpu().numpy()
+    # per-kernel device times: instrumented solves (eager, events around every launch)
+    nt = max(2, min(steps, 5))
+    tot = {"bessel_ms": 0.0, "product_ms": 0.0, "cl_ms": 0.0}
+    launches = 0
+    for _ in range(nt):
+        t = plan.los_batch_solve_timed(b.tau0, km, tau, w, S, wk, Pk, cl)
+        for key in tot:
+            tot[key] += t[key] / nt
+        launches = t["launches"]
     info = plan.los_batch_info()
+    return {"ms": ms, "first_ms": first_ms, "wall": wall, "cl": cl_host, "kernels": tot,
+            "launches": launches, "info": info, "prec": prec_name}
+
+
+def run_batch(args):
+    """C4: 256 drawn models on the shared 8000-point master k grid, one graph launch per step,
+    FP32 MFMA projection (the configured precision); split-BF16x3 on the same inputs as extra
+    keys; the FP64 plain path on a sample of the models; the CPU oracle on a bounded sample."""
+    import torch
+    from paper_2509_25110_amd import inputs, los
+    torch.cuda.set_device(0)
+    prec_name = args.prec or "fp32"
+    if prec_name == "fp64":
+        print("bench.py: C4 runs the MFMA precisions (fp32, bf16x3); the FP64 plain path is "
+              "reported beside them", file=sys.stderr)
+        sys.exit(2)
+    b = inputs.batch_inputs(inputs.draw_models(256))
+    ctx = los.Context()
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                prec=PRECS[prec_name])
+    col, ncols = plan.los_batch_columns()
+    S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
+    inputs.batch_sources_device(b, col, S, torch)
+    tp, dense = batch_tp_counts(b)
+    flops = 2.0 * 3 * tp                     # useful flops: 2 per FMA, 3 sources per TP entry
+    K = args.steps
+
+    def summary(r, peak_key):
+        peak = PEAK[peak_key]
+        pk = r["kernels"]["product_ms"]
+        achieved = flops / (pk * 1e-3) / 1e12
+        return {"value": b.nmodels / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+                "first_call_ms": r["first_ms"],
+                "kernel_ms": r["kernels"], "launches_per_step": r["launches"],
+                "max_rel_err_vs_oracle": golden_error_c4(r["cl"], b),
+                "tuned_shape": r["info"]["fused_shape"] if r["info"]["fused"] else
+                [r["info"]["tile_mb"], r["info"]["tile_nc"]],
+                "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                             "unit": "TFLOP/s", "frac": achieved / peak,
+                             "kernel": "fused_gemm_kernel" if r["info"]["fused"] else
+                             "mfma_gemm_kernel",
+                             "kernel_ms_per_step": pk,
+                             "whole_step_frac": flops / (r["ms"] * 1e-3) / 1e12 / peak}}
+
+    main = batch_run_prec(plan, b, S, dv, prec_name, K, args.warmup, torch)
+    info = main["info"]
+    plan.close()
+    msum = summary(main, "bf16x3_mfma" if prec_name == "bf16x3" else "fp32_mfma")
+    roof = dict(msum["roofline"])
+    roof["traffic"] = batch_traffic(roof["kernel"], "C4")
+    roof["work"] = ("2 x 3 sources x %d TP entries (useful FP32-equivalent flops) per step, "
+                    "over %d launches" % (tp, main["launches"]))
+    roof["peak_note"] = ("bf16x3: 2516.6 TF dense bf16 / 3" if prec_name == "bf16x3" else
+                         "dense FP32 MFMA")
     out = {
         "metric": METRIC,
-        "value": b.nmodels / (ms * 1e-3),
+        "value": msum["value"],
         "unit": "spectra/s",
-        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms,
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": main["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {1: "f64 j_l, f32 product", 2: "f64 j_l, bf16x3 product"}[prec],
+        "dtype": {"fp32": "f64 j_l, f32 product", "bf16x3": "f64 j_l, bf16x3 product"}[prec_name],
         "data": "synthetic",
-        "config": {"workload": "C4: %s, shared master k grid, %s MFMA, one graph launch per step"
-                               % (inputs.DESCRIPTIONS["C4"], args.prec if prec != 2 else "bf16x3"),
+        "config": {"workload": "C4: %s, shared master k grid, %s MFMA projection, Bessel tiles "
+                               "regenerated in LDS, one graph launch per step"
+                               % (inputs.DESCRIPTIONS["C4"], prec_name),
                    "models": b.nmodels, "packed_columns": ncols, "master_rows": info["rows"],
                    "ntau": b.ntau, "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "whole batch solve (jtable + mfma_gemm + batch_cl, graph)",
-                     "kernel_ms": ms,
-                     "work": "2 x 3 sources x %d TP entries (useful FP32-equivalent flops)" % tp,
-                     "peak_note": "bf16x3: 2516.6 TF dense bf16 / 3" if prec == 2 else
-                                  "dense FP32 MFMA"},
-        "gfma_per_s": 3 * tp / (ms * 1e-3) / 1e9,
+        "roofline": roof,
+        "gfma_per_s": 3 * tp / (main["ms"] * 1e-3) / 1e9,
         "tp_entries": tp, "dense_entries": dense,
-        "first_call_ms": first_ms, "wall_s_timed": wall,
-        "tile": [info["tile_mb"], info["tile_nc"]], "chunks": info["chunks"],
-        "max_rel_err_vs_oracle": err,
+        "first_call_ms": main["first_ms"], "wall_s_timed": main["wall"],
+        "kernel_ms_per_step": main["kernels"], "chunks": info["chunks"],
+        "tuned_shape": msum["tuned_shape"],
+        "max_rel_err_vs_oracle": msum["max_rel_err_vs_oracle"],
+        "oracle_models": "8 seeded models of the 256, every l (tests/golden/c4_cl_oracle.txt)",
     }
+    if not args.no_other_prec:
+        other = "bf16x3" if prec_name == "fp32" else "fp32"
+        plan2 = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                     prec=PRECS[other])
+        r2 = batch_run_prec(plan2, b, S, dv, other, K, args.warmup, torch)
+        plan2.close()
+        o = summary(r2, "bf16x3_mfma" if other == "bf16x3" else "fp32_mfma")
+        o["roofline"]["traffic"] = None
+        out[other] = o
+    if not args.no_fp64_compare:
+        # the FP64 plain path on models of the batch solved one by one, scaled by TP work
+        sample = [0, 3, 100, 200]
+        tsum = 0.0
+        for i in sample:
+            wlm = inputs.model_workload(b.draws[i])
+            a64 = [dv(wlm.k), dv(wlm.tau), wlm.tau0, dv(wlm.w_tau), dv(wlm.S)]
+            wk, Pk = dv(wlm.w_lnk), dv(wlm.Pk)
+            dd = ctx.los_project(wlm.lmin, wlm.lmax, *a64)
+            ctx.cl_integrate(dd, wk, Pk, wlm.pairs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.los_project(wlm.lmin, wlm.lmax, *a64, delta=dd)
+            ctx.cl_integrate(dd, wk, Pk, wlm.pairs)
+            torch.cuda.synchronize()
+            tsum += time.perf_counter() - t0
+            del dd
+        tp_sub, _ = batch_tp_counts(inputs.batch_inputs([b.draws[i] for i in sample]))
+        fp64 = b.nmodels / (tsum * tp / tp_sub)
+        out["fp64_plain_path"] = {"value": fp64, "unit": "spectra/s",
+                                  "sample": "models %s solved one by one with the FP64 path "
+                                            "(%.3f s), scaled to the batch by TP work"
+                                            % (sample, tsum)}
+        out["speedup_vs_fp64_plain_path"] = out["value"] / fp64
+        if "bf16x3" in out:
+            out["bf16x3"]["speedup_vs_fp64_plain_path"] = out["bf16x3"]["value"] / fp64
     if not args.no_cpu_baseline:
         import oracle
         m = 3
@@ -251,28 +348,7 @@ def run_batch(args):
                                "sample": "model %d, every 32nd of its %d k rows, all l and tau: "
                                          "%.1f s; scaled by the batch's dense (k, tau, l) count"
                                          % (m, wlm.nk, dt)}
-    if args.fp64_compare:
-        # the FP64 plain path on a few models of the batch, scaled by their share of TP work
-        sample = [0, 3, 100, 200]
-        tsum = 0.0
-        for i in sample:
-            wlm = inputs.model_workload(b.draws[i])
-            args64 = [dv(wlm.k), dv(wlm.tau), wlm.tau0, dv(wlm.w_tau), dv(wlm.S)]
-            ctx.los_project(wlm.lmin, wlm.lmax, args64[0], args64[1], args64[2], args64[3],
-                            args64[4])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            dd = ctx.los_project(wlm.lmin, wlm.lmax, args64[0], args64[1], args64[2], args64[3],
-                                 args64[4])
-            ctx.cl_integrate(dd, dv(wlm.w_lnk), dv(wlm.Pk), wlm.pairs)
-            torch.cuda.synchronize()
-            tsum += time.perf_counter() - t0
-            del dd
-        tp_sub, _ = batch_tp_counts(inputs.batch_inputs([b.draws[i] for i in sample]))
-        out["fp64_plain_path"] = {"value": b.nmodels / (tsum * tp / tp_sub), "unit": "spectra/s",
-                                  "sample": "models %s solved one by one with the FP64 path "
-                                            "(%.3f s), scaled by TP work" % (sample, tsum)}
-    plan.close()
+    del S
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -429,15 +505,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--prec", default="fp64", choices=list(PRECS))
+    ap.add_argument("--config", default="C4",
+                    help="C4 (default: the 256-model batch), C5 (emulator), C1/C2/C3 (one model)")
+    ap.add_argument("--prec", default=None, choices=list(PRECS),
+                    help="default fp32 for C4, fp64 for C1-C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle sample: every n-th k row (default 1 for C2, 4 for C3)")
     ap.add_argument("--emu-train", type=int, default=4096, help="C5: training spectra")
     ap.add_argument("--emu-epochs", type=int, default=300, help="C5: training epochs")
-    ap.add_argument("--fp64-compare", action="store_true",
-                    help="C4: also time the FP64 plain path on a sample of the batch's models")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="C4: skip timing the FP64 plain path on a sample of the batch's models")
+    ap.add_argument("--no-other-prec", action="store_true",
+                    help="C4: skip the second MFMA precision (bf16x3 beside fp32)")
     ap.add_argument("--lsample", type=float, default=0.0,
                     help="C2/C3 FP64: compute the multipoles of inputs.l_samples(boost) only and "
                          "interpolate C_l (los_project_lsample + cl_integrate + los_cl_interp)")
@@ -472,7 +552,7 @@ def main():
 
     torch.cuda.set_device(0)
     wl = inputs.config(args.config)
-    prec = PRECS[args.prec]
+    prec = PRECS[args.prec or "fp64"]
     sdt = np.float64 if prec == 0 else np.float32
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     k, tau, w, S = dv(wl.k), dv(wl.tau), dv(wl.w_tau), dv(wl.S.astype(sdt))

@@ -116,11 +116,15 @@ int los_bessel_table(los_ctx *ctx, const double *x, int64_t nx, int32_t lmin, in
  * the band where |j_l| < ~1e-21 of its peak is skipped.
  * LOS_FP32 / LOS_BF16X3 (Sec. 2.1 Eq. 2-3 as the per-k matrix product
  * Delta_k[l][s] = sum_n J_k[l][n] S[s][k][n], J_k[l][n] = w_n j_l(k chi_n)):
- * the tables J_k are built in FP64 (downward recurrence from the band edge,
- * upward recurrence for the seeds), rounded to FP32 and kept in a context
- * workspace of at most LOS_JTAB_MIB MiB (environment, default 4096) for a
- * chunk of k rows, then multiplied on the matrix cores with FP32
- * accumulation.  Expected C_l error ~1e-6 relative (both precisions).
+ * J_k is computed in FP64 (downward recurrence from the band edge, upward
+ * recurrence for the normalisation) and rounded to FP32 as it is used.  By
+ * default a first kernel keeps only the FP64 recurrence state every 32
+ * multipoles (a context workspace of at most LOS_JTAB_MIB MiB, environment,
+ * default 4096, per chunk of k rows) and the product kernel regenerates each
+ * tile of J_k from it in on-chip memory, multiplying on the matrix cores with
+ * FP32 accumulation; LOS_MIXED_FUSED=0 selects whole FP32 tables in the
+ * workspace instead.  Both give the same values.  Expected C_l error ~1e-6
+ * relative (both precisions).
  * Errors: LOS_ERR_OOM if the workspace cannot be allocated.
  */
 int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
@@ -245,13 +249,17 @@ int los_interp_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, co
  * one tau grid; model m uses master rows k_index[koff[m] .. koff[m+1]-1]
  * (strictly increasing) and multipoles l = 2..lmax[m].  For every master row,
  * the sources of all models that use it form the columns of one matrix
- * product J_k . S_k (J_k built once, FP64 then FP32), computed on the matrix
- * cores in `prec` (LOS_FP32 or LOS_BF16X3), and each model's C_l are summed
- * over its own k in FP64.
+ * product J_k . S_k (J_k generated once per l tile, FP64 then FP32),
+ * computed on the matrix cores in `prec` (LOS_FP32 or LOS_BF16X3), and each
+ * model's C_l are summed over its own k in FP64.  By default the Bessel
+ * tiles are regenerated in LDS from FP64 recurrence seeds kept every 32
+ * multipoles (no Bessel table in device memory); environment
+ * LOS_BATCH_FUSED=0 at plan creation selects whole FP32 tables instead.
  *
  * los_batch_create (host arrays; allocates the plan's device tables and a
- * workspace of at most LOS_JTAB_MIB MiB of Bessel tables plus one chunk of
- * products): lmax[nmodels] in [2, 16000]; koff[nmodels+1] with koff[0] = 0
+ * workspace of at most LOS_BATCH_MIB MiB (default 8192) of seeds plus
+ * products -- with LOS_BATCH_FUSED=0, LOS_JTAB_MIB MiB (default 4096) of
+ * Bessel tables plus one chunk of products): lmax[nmodels] in [2, 16000]; koff[nmodels+1] with koff[0] = 0
  * and koff[m+1] > koff[m]; k_index[koff[nmodels]] in [0, nk_master);
  * pairs[2*npairs] source indices (1 <= npairs <= 16, 1 <= nsrc <= 4);
  * 1 <= ntau <= 8192.  *plan receives a handle released by los_batch_destroy.
@@ -271,12 +279,15 @@ int los_interp_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, co
  *   cl[nmodels * npairs * (L - 1)] (double, written), L = max lmax:
  *     cl[(m * npairs + p) * (L - 1) + l - 2] = 4 pi sum_j w P Delta^a Delta^b,
  *     zero for l > lmax[m].
- * The first call times every compiled tile shape (including an LDS-staged
- * 256 x 128 split-BF16x3 kernel) on two representative chunks and keeps the
- * fastest; each new set of argument pointers is captured once into a HIP
- * graph that later calls replay.  A plan is not thread-safe.
- * los_batch_info (host): info[8] = {tile l blocks, tile column blocks, rows
- * per chunk, chunks, used master rows, max lmax, tuned, graph captured}.
+ * The first call times every compiled tile shape of the pipeline (fused:
+ * 256 x 128, 128 x 128 and 256 x 256 l x column tiles; tables: fragment
+ * tiles and an LDS-staged 256 x 128 split-BF16x3 kernel) on two
+ * representative chunks and keeps the fastest; each new set of argument
+ * pointers is captured once into a HIP graph that later calls replay.  A
+ * plan is not thread-safe.
+ * los_batch_info (host): info[10] = {tile l blocks, tile column blocks
+ * (table pipeline), rows per chunk, chunks, used master rows, max lmax,
+ * tuned, graph captured, fused pipeline (1/0), fused shape index}.
  */
 typedef struct los_batch los_batch;
 
@@ -291,6 +302,20 @@ int los_batch_info(const los_batch *plan, int32_t *info);
 int los_batch_solve(los_batch *plan, double tau0, const double *k_master, const double *tau,
                     const double *w_tau, const float *S_packed, const double *w_lnk,
                     const double *Pk, double *cl, void *stream);
+
+/*
+ * Instrumented solve (for measurement; not to be called under stream
+ * capture): the same launches as los_batch_solve, enqueued directly on
+ * `stream` (no graph) with HIP events around each kernel; returns after the
+ * stream has reached the last event.  ms (host, 3 doubles) receives the
+ * summed device time of the Bessel kernels (seeds or tables), the product
+ * kernels and the C_l kernels; launches (host, 3 int32) their launch counts
+ * (one each per chunk).  cl and the other arguments as for los_batch_solve.
+ */
+int los_batch_solve_timed(los_batch *plan, double tau0, const double *k_master,
+                          const double *tau, const double *w_tau, const float *S_packed,
+                          const double *w_lnk, const double *Pk, double *cl, double *ms,
+                          int32_t *launches, void *stream);
 
 void los_batch_destroy(los_batch *plan);
 

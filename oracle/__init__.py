@@ -35,14 +35,32 @@ _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int32_p = ctypes.POINTER(ctypes.c_int32)
 
 
+_SHA_PATH = _LIB_PATH + ".src-sha256"
+
+
+def _src_sha() -> str:
+    import hashlib
+    with open(_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def build(force: bool = False) -> str:
-    """Compile ``los_oracle.c`` into ``liblos_oracle.so`` (gcc -O2 -fopenmp, no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    """Compile ``los_oracle.c`` into ``liblos_oracle.so`` (gcc -O2 -fopenmp, no fast-math).
+    Without ``force`` the library is rebuilt only when it is missing or was built from other
+    source text (a hash kept beside it; file times are not used, since copies reorder them)."""
+    sha = _src_sha()
+    stale = not os.path.exists(_LIB_PATH) or not os.path.exists(_SHA_PATH)
+    if not stale:
+        with open(_SHA_PATH) as f:
+            stale = f.read().strip() != sha
+    if force or stale:
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-fno-fast-math",
                "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
+        with open(_SHA_PATH, "w") as f:
+            f.write(sha + "\n")
     return _LIB_PATH
 
 

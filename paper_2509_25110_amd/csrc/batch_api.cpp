@@ -8,11 +8,15 @@
 // each row's columns are the (model, source) pairs that use it, ordered by
 // model l_max (largest first) so a 16-column block can stop at the l_max of
 // its first column.  Rows are processed in chunks that fit a bounded device
-// workspace: Bessel tables (jtable.hip) -> MFMA product with transposed
-// output (project_mfma.hip) -> per-model C_l accumulation (batch_cl.hip).
-// The first solve times every compiled tile shape on two representative
-// chunks and keeps the fastest (autotuner); the whole launch sequence is then
-// captured once into a HIP graph per set of argument pointers and replayed.
+// workspace.  Default pipeline per chunk: Bessel seeds (jseed_kernel) ->
+// product with the Bessel tiles regenerated in LDS and transposed output
+// (fused_gemm_kernel, project_fused.hip) -> per-model C_l accumulation
+// (batch_cl.hip).  LOS_BATCH_FUSED=0 selects the table pipeline instead:
+// whole FP32 Bessel tables in HBM (jtable.hip) -> MFMA product
+// (project_mfma*.hip).  The first solve times every compiled tile shape of
+// the pipeline on two representative chunks and keeps the fastest
+// (autotuner); the whole launch sequence is then captured once into a HIP
+// graph per set of argument pointers and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,6 +49,13 @@ struct los_batch {
   int *d_col_cnt = nullptr, *d_col_lmax = nullptr, *d_lmax = nullptr;
   float *J = nullptr, *D = nullptr;
   int *top = nullptr;
+  // fused pipeline: seeds workspace (J unused)
+  bool fused = true;
+  int nseg = 0;
+  int64_t ntp64 = 0;
+  void *seedws = nullptr;
+  int fshape = 0;
+  float ftune_ms[los::kFusedShapeCount] = {};
   std::vector<int64_t> chunk_col0;  // packed column at the start of each chunk
   // tuning and graph
   los::GemmTile tile{2, 4};
@@ -79,7 +90,7 @@ void free_plan(los_batch *b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   // `top` lives inside the J allocation
   void *ptrs[] = {b->d_rows, b->d_col_off, b->d_pos_col, b->d_koff, b->d_jr, b->d_col_cnt,
-                  b->d_col_lmax, b->d_lmax, b->J, b->D};
+                  b->d_col_lmax, b->d_lmax, b->J, b->D, b->seedws};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -136,17 +147,60 @@ los::GemmArgs gargs(const los_batch *b, const SolveArgs &s, int c) {
   return a;
 }
 
+los::FusedArgs fargs(const los_batch *b, const SolveArgs &s, int c) {
+  los::FusedArgs a{};
+  a.lmin = b->lmin;
+  a.lmax = b->lmax_g;
+  a.nl = b->nl;
+  a.nlb = b->nlb;
+  a.nseg = b->nseg;
+  a.ntau = b->ntau;
+  a.ntp = b->ntp64;
+  a.k0 = b->chunk_row0[c];
+  a.row_index = b->d_rows;
+  a.tau0 = s.tau0;
+  a.k = s.k;
+  a.tau = s.tau;
+  a.w = s.w;
+  los::fused_workspace_at(a, b->seedws, (int)(b->chunk_row0[c + 1] - b->chunk_row0[c]));
+  a.S = s.S;
+  a.s_cstride = b->ntau;
+  a.col_cnt = b->d_col_cnt;
+  a.col_off = b->d_col_off;
+  a.col_base = b->chunk_col0[c];
+  a.col_lmax = b->d_col_lmax;
+  a.dtrans = 1;
+  a.delta = b->D;
+  return a;
+}
+
+// The product of chunk c: J . S for the chunk's rows into D (either pipeline).
+int enqueue_product(los_batch *b, const SolveArgs &s, int c, hipStream_t st) {
+  const int64_t r0 = b->chunk_row0[c];
+  const int cnt = (int)(b->chunk_row0[c + 1] - r0);
+  hipError_t e;
+  if (b->fused) {
+    const los::FusedArgs fa = fargs(b, s, c);
+    e = los::jseed_launch(fa, cnt, st);
+    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: Bessel seed launch");
+    e = los::fused_gemm_launch(fa, b->prec, b->fshape, cnt, b->chunk_maxcol[c], st);
+    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: fused product launch");
+    return LOS_OK;
+  }
+  e = los::jtable_launch(jargs(b, s, r0), cnt, st);
+  if (e != hipSuccess) return hip_fail(e, "los_batch_solve: Bessel table launch");
+  e = los::mfma_gemm_launch(gargs(b, s, c), b->prec, b->tile, cnt, b->chunk_maxcol[c], st);
+  if (e != hipSuccess) return hip_fail(e, "los_batch_solve: MFMA product launch");
+  return LOS_OK;
+}
+
 // Enqueue the whole solve on stream st.
 int enqueue(los_batch *b, const SolveArgs &s, hipStream_t st) {
   hipError_t e = los::fill_zero_launch(s.cl, (int64_t)b->nmodels * b->npairs * b->nl, st);
   if (e != hipSuccess) return hip_fail(e, "los_batch_solve: fill launch");
   for (int c = 0; c < b->nchunks; ++c) {
-    const int64_t r0 = b->chunk_row0[c];
-    const int cnt = (int)(b->chunk_row0[c + 1] - r0);
-    e = los::jtable_launch(jargs(b, s, r0), cnt, st);
-    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: Bessel table launch");
-    e = los::mfma_gemm_launch(gargs(b, s, c), b->prec, b->tile, cnt, b->chunk_maxcol[c], st);
-    if (e != hipSuccess) return hip_fail(e, "los_batch_solve: MFMA product launch");
+    int rc = enqueue_product(b, s, c, st);
+    if (rc != LOS_OK) return rc;
     los::BatchClArgs ca{};
     ca.nmodels = b->nmodels;
     ca.nsrc = b->nsrc;
@@ -171,11 +225,80 @@ int enqueue(los_batch *b, const SolveArgs &s, hipStream_t st) {
   return LOS_OK;
 }
 
-// Time every compiled tile shape on two representative chunks (the middle
-// one and the last full one, where k and the Bessel band are largest), each
-// after building its Bessel table once; keep the fastest total.
+// Fused pipeline: time the wide fused shapes (0..3) on two representative
+// chunks after building their seeds once; keep the fastest total.
+// LOS_BATCH_SHAPE pins a shape; LOS_BATCH_TUNE=0 keeps shape 0.
+int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
+  const char *pin = std::getenv("LOS_BATCH_SHAPE");
+  if (pin) {
+    const int sh = std::atoi(pin);
+    if (sh < 0 || sh >= los::kFusedShapeCount)
+      return fail(LOS_ERR_INVALID, "los_batch_solve: fused shape %d is not compiled", sh);
+    b->fshape = sh;
+    b->tuned = true;
+    return LOS_OK;
+  }
+  if (!env_i("LOS_BATCH_TUNE", 1)) {
+    b->tuned = true;
+    return LOS_OK;
+  }
+  int probe[2] = {b->nchunks / 2, b->nchunks - 1};
+  if (b->nchunks > 1 && b->chunk_row0[b->nchunks] - b->chunk_row0[b->nchunks - 1] < b->kc)
+    probe[1] = b->nchunks - 2;
+  const int nprobe = probe[0] == probe[1] ? 1 : 2;
+  hipEvent_t t0, t1;
+  hipError_t e;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return hip_fail(e, "autotune: event");
+  if ((e = hipEventCreate(&t1)) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return hip_fail(e, "autotune: event");
+  }
+  constexpr int kWide = 4;  // shapes 0..3 have at least 128 columns
+  float total[kWide] = {};
+  int rc = LOS_OK;
+  for (int pi = 0; pi < nprobe && rc == LOS_OK; ++pi) {
+    const int c = probe[pi];
+    const int cnt = (int)(b->chunk_row0[c + 1] - b->chunk_row0[c]);
+    const los::FusedArgs fa = fargs(b, s, c);
+    e = los::jseed_launch(fa, cnt, st);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "autotune: Bessel seed launch");
+      break;
+    }
+    for (int i = 0; i < kWide && rc == LOS_OK; ++i) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && rc == LOS_OK; ++rep) {  // first run warms up
+        e = hipEventRecord(t0, st);
+        if (e == hipSuccess) e = los::fused_gemm_launch(fa, b->prec, i, cnt, b->chunk_maxcol[c], st);
+        if (e == hipSuccess) e = hipEventRecord(t1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e != hipSuccess) rc = hip_fail(e, "autotune");
+      }
+      total[i] += ms;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc != LOS_OK) return rc;
+  float best = 1e30f;
+  for (int i = 0; i < kWide; ++i) {
+    b->ftune_ms[i] = total[i];
+    if (total[i] < best) {
+      best = total[i];
+      b->fshape = i;
+    }
+  }
+  b->tuned = true;
+  return LOS_OK;
+}
+
+// Table pipeline: time every compiled tile shape on two representative chunks
+// (the middle one and the last full one, where k and the Bessel band are
+// largest), each after building its Bessel table once; keep the fastest total.
 // LOS_BATCH_TILE_MB / _NC pin a shape instead; LOS_BATCH_TUNE=0 keeps {2, 4}.
 int autotune(los_batch *b, const SolveArgs &s, hipStream_t st) {
+  if (b->fused) return autotune_fused(b, s, st);
   const int mb = env_i("LOS_BATCH_TILE_MB", 0), nc = env_i("LOS_BATCH_TILE_NC", 0);
   if (mb > 0 && nc > 0) {
     los::GemmTile t{mb, nc};
@@ -350,21 +473,53 @@ int los_batch_create(los_ctx *ctx, int32_t nmodels, int32_t nsrc, const int32_t 
   b->ncols = col;
   b->nrows = (int64_t)rows.size();
 
-  // chunks of rows: Bessel tables within LOS_JTAB_MIB (default 4096 MiB)
+  // chunks of rows.  Table pipeline: Bessel tables within LOS_JTAB_MIB
+  // (default 4096 MiB).  Fused pipeline: seeds plus the chunk's products
+  // within LOS_BATCH_MIB (default 8192 MiB).
+  b->fused = env_i("LOS_BATCH_FUSED", 1) != 0;
+  b->nseg = (b->nlb + 1) / 2;
+  b->ntp64 = (ntau + 63) / 64 * 64;
   const size_t jrow = sizeof(float) * (size_t)b->nlp * b->ntp + sizeof(int) * b->ntb;
-  int64_t mib = env_i("LOS_JTAB_MIB", 4096);
-  if (mib < 1) mib = 1;
-  b->kc = std::max<int64_t>(1, std::min<int64_t>((int64_t)((size_t)mib * (1u << 20) / jrow), 65535));
-  b->kc = std::min(b->kc, b->nrows);
+  const size_t srow = los::fused_seed_bytes_per_row(b->nseg, b->ntp64);
   size_t dmax = 0;
-  for (int64_t r0 = 0; r0 < b->nrows; r0 += b->kc) {
-    const int64_t r1 = std::min(b->nrows, r0 + b->kc);
-    b->chunk_row0.push_back(r0);
-    b->chunk_col0.push_back(col_off[r0]);
-    int mc = 0;
-    for (int64_t r = r0; r < r1; ++r) mc = std::max(mc, col_cnt[r]);
-    b->chunk_maxcol.push_back(mc);
-    dmax = std::max(dmax, (size_t)(col_off[r1] - col_off[r0]) * b->nl);
+  if (b->fused) {
+    int64_t mib = env_i("LOS_BATCH_MIB", 8192);
+    if (mib < 1) mib = 1;
+    const size_t budget = (size_t)mib << 20;
+    int64_t r0 = 0;
+    b->kc = 0;
+    while (r0 < b->nrows) {
+      int64_t r1 = r0;
+      size_t used = 0;
+      while (r1 < b->nrows && r1 - r0 < 65535) {
+        const size_t add = srow + sizeof(float) * (size_t)col_cnt[r1] * b->nl;
+        if (r1 > r0 && used + add > budget) break;
+        used += add;
+        ++r1;
+      }
+      b->chunk_row0.push_back(r0);
+      b->chunk_col0.push_back(col_off[r0]);
+      int mc = 0;
+      for (int64_t r = r0; r < r1; ++r) mc = std::max(mc, col_cnt[r]);
+      b->chunk_maxcol.push_back(mc);
+      dmax = std::max(dmax, (size_t)(col_off[r1] - col_off[r0]) * b->nl);
+      b->kc = std::max(b->kc, r1 - r0);
+      r0 = r1;
+    }
+  } else {
+    int64_t mib = env_i("LOS_JTAB_MIB", 4096);
+    if (mib < 1) mib = 1;
+    b->kc = std::max<int64_t>(1, std::min<int64_t>((int64_t)((size_t)mib * (1u << 20) / jrow), 65535));
+    b->kc = std::min(b->kc, b->nrows);
+    for (int64_t r0 = 0; r0 < b->nrows; r0 += b->kc) {
+      const int64_t r1 = std::min(b->nrows, r0 + b->kc);
+      b->chunk_row0.push_back(r0);
+      b->chunk_col0.push_back(col_off[r0]);
+      int mc = 0;
+      for (int64_t r = r0; r < r1; ++r) mc = std::max(mc, col_cnt[r]);
+      b->chunk_maxcol.push_back(mc);
+      dmax = std::max(dmax, (size_t)(col_off[r1] - col_off[r0]) * b->nl);
+    }
   }
   b->chunk_row0.push_back(b->nrows);
   b->nchunks = (int)b->chunk_row0.size() - 1;
@@ -394,7 +549,8 @@ int los_batch_create(los_ctx *ctx, int32_t nmodels, int32_t nsrc, const int32_t 
   if (rc == LOS_OK) rc = dev_copy(&b->d_lmax, lmax_v.data(), lmax_v.size());
   if (rc == LOS_OK) rc = dev_copy(&b->d_jr, jr.data(), jr.size());
   if (rc == LOS_OK) {
-    hipError_t e = hipMalloc((void **)&b->J, jrow * (size_t)b->kc);
+    hipError_t e = b->fused ? hipMalloc(&b->seedws, srow * (size_t)b->kc)
+                            : hipMalloc((void **)&b->J, jrow * (size_t)b->kc);
     if (e == hipSuccess) e = hipMalloc((void **)&b->D, sizeof(float) * (dmax ? dmax : 1));
     if (e != hipSuccess) rc = fail(LOS_ERR_OOM, "los_batch_create: workspace: %s", hipGetErrorString(e));
     if (b->J)
@@ -429,6 +585,8 @@ int los_batch_info(const los_batch *plan, int32_t *info) {
   info[5] = plan->lmax_g;
   info[6] = plan->tuned ? 1 : 0;
   info[7] = plan->exec ? 1 : 0;
+  info[8] = plan->fused ? 1 : 0;
+  info[9] = plan->fshape;
   return ok();
 }
 
@@ -478,6 +636,87 @@ int los_batch_solve(los_batch *plan, double tau0, const double *k_master, const 
   }
   hipError_t e = hipGraphLaunch(plan->exec, st);
   if (e != hipSuccess) return hip_fail(e, "los_batch_solve: graph launch");
+  return ok();
+}
+
+int los_batch_solve_timed(los_batch *plan, double tau0, const double *k_master,
+                          const double *tau, const double *w_tau, const float *S_packed,
+                          const double *w_lnk, const double *Pk, double *cl, double *ms,
+                          int32_t *launches, void *stream) {
+  if (!plan) return fail(LOS_ERR_INVALID, "los_batch_solve_timed: plan is NULL");
+  if (!k_master || !tau || !w_tau || !S_packed || !w_lnk || !Pk || !cl || !ms || !launches)
+    return fail(LOS_ERR_INVALID, "los_batch_solve_timed: NULL array");
+  if (!(tau0 == tau0)) return fail(LOS_ERR_INVALID, "los_batch_solve_timed: tau0 is NaN");
+  hipStream_t st = (hipStream_t)stream;
+  SolveArgs s{tau0, k_master, tau, w_tau, S_packed, w_lnk, Pk, cl};
+  if (!plan->tuned) {
+    int rc = autotune(plan, s, st);
+    if (rc != LOS_OK) return rc;
+  }
+  // events: ev[0] before the first chunk, then after the Bessel kernel, the
+  // product and the C_l kernel of every chunk
+  std::vector<hipEvent_t> ev(3 * (size_t)plan->nchunks + 1, nullptr);
+  int rc = LOS_OK;
+  hipError_t e = hipSuccess;
+  for (auto &x : ev)
+    if ((e = hipEventCreate(&x)) != hipSuccess) break;
+  if (e == hipSuccess) e = los::fill_zero_launch(cl, (int64_t)plan->nmodels * plan->npairs * plan->nl, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+  for (int c = 0; c < plan->nchunks && e == hipSuccess && rc == LOS_OK; ++c) {
+    const int64_t r0 = plan->chunk_row0[c];
+    const int cnt = (int)(plan->chunk_row0[c + 1] - r0);
+    if (plan->fused) {
+      const los::FusedArgs fa = fargs(plan, s, c);
+      e = los::jseed_launch(fa, cnt, st);
+      if (e == hipSuccess) e = hipEventRecord(ev[3 * c + 1], st);
+      if (e == hipSuccess)
+        e = los::fused_gemm_launch(fa, plan->prec, plan->fshape, cnt, plan->chunk_maxcol[c], st);
+    } else {
+      e = los::jtable_launch(jargs(plan, s, r0), cnt, st);
+      if (e == hipSuccess) e = hipEventRecord(ev[3 * c + 1], st);
+      if (e == hipSuccess)
+        e = los::mfma_gemm_launch(gargs(plan, s, c), plan->prec, plan->tile, cnt,
+                                  plan->chunk_maxcol[c], st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[3 * c + 2], st);
+    if (e != hipSuccess) break;
+    los::BatchClArgs ca{};
+    ca.nmodels = plan->nmodels;
+    ca.nsrc = plan->nsrc;
+    ca.npairs = plan->npairs;
+    ca.lmin = plan->lmin;
+    ca.nl = plan->nl;
+    ca.chunk = c;
+    std::memcpy(ca.pa, plan->pa, sizeof ca.pa);
+    std::memcpy(ca.pb, plan->pb, sizeof ca.pb);
+    ca.lmax = plan->d_lmax;
+    ca.koff = plan->d_koff;
+    ca.jr = plan->d_jr;
+    ca.pos_col = plan->d_pos_col;
+    ca.col_base = plan->chunk_col0[c];
+    ca.D = plan->D;
+    ca.w_lnk = w_lnk;
+    ca.Pk = Pk;
+    ca.cl = cl;
+    e = los::batch_cl_launch(ca, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[3 * c + 3], st);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < plan->nchunks && e == hipSuccess; ++c) {
+    for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[3 * c + q], ev[3 * c + q + 1]);
+      acc[q] += t;
+    }
+  }
+  for (auto &x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(e, "los_batch_solve_timed");
+  for (int q = 0; q < 3; ++q) {
+    ms[q] = acc[q];
+    launches[q] = plan->nchunks;
+  }
   return ok();
 }
 

@@ -111,4 +111,47 @@ __device__ inline void run_down(double &hn, double &hc, int l0, int l1, double i
   }
 }
 
+// Normalised pair at a node's top row, the start of a descending sweep over
+// rows lmin..lmax in 16-row blocks (Bessel tables and the fused projection).
+// For x = k chi (x >= kXTiny) and weight wt: R is the top row of the 16-row
+// block (counted from lmin) that holds min(ltop(x), lmax), and on return
+// (cur, nxt) = wt (j_R, j_{R+1}):
+//   * x >= lmax + 1: upward recurrence from j_0 = sin x / x, j_{-1} = cos x / x
+//     (stable on the oscillatory side) up to l = R + 1 (R is at most 15 rows
+//     past lmax; those rows are never stored);
+//   * otherwise: upward to m = floor(x) for j_m, and Miller's downward
+//     recurrence from max(ltop(x), R) with seeds (0, 1) down to m, scaled
+//     there by j_m (near the last maximum in l, never near a zero).
+// Returns R, or -1 when no row in [lmin, lmax] is inside the band.
+__device__ inline int node_top_pair(double x, double ix, double wt, int lmin, int lmax,
+                                    double &cur, double &nxt) {
+  cur = 0.0;
+  nxt = 0.0;
+  const int m = (int)x;
+  const int L0 = ltop_of(x);
+  double s, c;
+  sincos(x, &s, &c);
+  double p = c * ix, q = s * ix;  // j_{l-1}, j_l at l = 0
+  if (m >= lmax + 1) {
+    const int R = lmin + (lmax - lmin) / 16 * 16 + 15;
+    run_up(p, q, 0, R + 1, ix);
+    cur = wt * p;
+    nxt = wt * q;
+    return R;
+  }
+  run_up(p, q, 0, m, ix);
+  const double jm = q;
+  const int Rc = min(L0, lmax);
+  if (Rc < lmin) return -1;
+  const int R = lmin + (Rc - lmin) / 16 * 16 + 15;
+  double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l
+  run_down(hn, hc, max(L0, R), R, ix);
+  const double hR = hc, hR1 = hn;
+  run_down(hn, hc, R, m, ix);
+  const double sc = wt * jm / hc;
+  cur = sc * hR;
+  nxt = sc * hR1;
+  return R;
+}
+
 }  // namespace los

@@ -56,36 +56,11 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
     const double wt = a.w[n];
     if (x >= kXTiny && wt != 0.0) {
       ix = 1.0 / x;
-      const int m = (int)x;
-      const int L0 = ltop_of(x);
-      double s, c;
-      sincos(x, &s, &c);
-      double p = c * ix, q = s * ix;  // j_{l-1}, j_l at l = 0
       // R is the top row of the 16-row block holding min(ltop(x), lmax): a lane
       // is then live either throughout a block or not at all.  Rows between
       // the band edge and R hold values below the band cut; rows past lmax
       // (at most 15, inside the padded table) are never stored by the product.
-      if (m >= a.lmax + 1) {
-        R = a.lmin + (a.lmax - a.lmin) / 16 * 16 + 15;
-        run_up(p, q, 0, R + 1, ix);
-        cur = wt * p;
-        nxt = wt * q;
-      } else {
-        run_up(p, q, 0, m, ix);
-        const double jm = q;
-        const int Rc = min(L0, a.lmax);
-        if (Rc >= a.lmin) {
-          R = a.lmin + (Rc - a.lmin) / 16 * 16 + 15;
-          // Miller from (0, 1) at max(L0, R): on to the top row R, then on to m
-          double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l
-          run_down(hn, hc, max(L0, R), R, ix);
-          const double hR = hc, hR1 = hn;
-          run_down(hn, hc, R, m, ix);
-          const double sc = wt * jm / hc;
-          cur = sc * hR;
-          nxt = sc * hR1;
-        }
-      }
+      R = node_top_pair(x, ix, wt, a.lmin, a.lmax, cur, nxt);
     }
   }
 

@@ -118,8 +118,57 @@ los::GemmTile gemm_tile_for(int max_ncol) {
   return {2, 4};
 }
 
-// Mixed-precision projection: FP64 Bessel tables (w folded in, rounded to
-// FP32) in chunks of k rows, each followed by the MFMA product with S.
+// Mixed-precision projection, default pipeline: per chunk of k rows the FP64
+// Bessel seeds (every 32 multipoles), then the product with the Bessel tiles
+// regenerated in LDS (project_fused.hip); no table reaches device memory.
+// The seed workspace is bounded by LOS_JTAB_MIB (default 4096 MiB);
+// LOS_FUSED_SHAPE picks the tile shape (default 4: 256 l x 16 columns).
+int project_mixed_fused(los_ctx *ctx, int lmin, int lmax, int64_t nk, int64_t ntau, double tau0,
+                        const double *k, const double *tau, const double *w_tau, const float *S,
+                        int nsrc, int prec, float *delta, hipStream_t stream) {
+  los::FusedArgs fa{};
+  fa.lmin = lmin;
+  fa.lmax = lmax;
+  fa.nl = lmax - lmin + 1;
+  fa.nlb = (fa.nl + 15) / 16;
+  fa.nseg = (fa.nlb + 1) / 2;
+  fa.ntau = ntau;
+  fa.ntp = (ntau + 63) / 64 * 64;
+  fa.row_index = nullptr;
+  fa.tau0 = tau0;
+  fa.k = k;
+  fa.tau = tau;
+  fa.w = w_tau;
+  fa.S = S;
+  fa.s_kstride = ntau;
+  fa.s_cstride = nk * ntau;
+  fa.ncol = nsrc;
+  fa.dtrans = 0;
+  fa.delta = delta;
+  const size_t per_k = los::fused_seed_bytes_per_row(fa.nseg, fa.ntp);
+  const int64_t kc = jtab_chunk(nk, per_k);
+  void *ws = nullptr;
+  int rc = ws_reserve(ctx, WS_JTAB, per_k * (size_t)kc, &ws);
+  if (rc != LOS_OK) return rc;
+  const char *sv = std::getenv("LOS_FUSED_SHAPE");
+  const int shape = sv ? std::atoi(sv) : 4;
+  if (shape < 0 || shape >= los::kFusedShapeCount)
+    return fail(LOS_ERR_INVALID, "los_project: fused shape %d is not compiled", shape);
+  for (int64_t k0 = 0; k0 < nk; k0 += kc) {
+    const int cnt = (int)(nk - k0 < kc ? nk - k0 : kc);
+    fa.k0 = k0;
+    los::fused_workspace_at(fa, ws, cnt);
+    hipError_t e = los::jseed_launch(fa, cnt, stream);
+    if (e != hipSuccess) return hip_fail(e, "los_project: Bessel seed launch");
+    e = los::fused_gemm_launch(fa, prec, shape, cnt, nsrc, stream);
+    if (e != hipSuccess) return hip_fail(e, "los_project: fused product launch");
+  }
+  return ok();
+}
+
+// Mixed-precision projection, table pipeline (LOS_MIXED_FUSED=0): FP64 Bessel
+// tables (w folded in, rounded to FP32) in chunks of k rows, each followed by
+// the MFMA product with S.
 int project_mixed(los_ctx *ctx, int lmin, int lmax, int64_t nk, int64_t ntau, double tau0,
                   const double *k, const double *tau, const double *w_tau, const float *S,
                   int nsrc, int prec, float *delta, hipStream_t stream) {
@@ -247,8 +296,12 @@ int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, in
   if (prec != LOS_FP64) {
     if (kernel_mask != 0)
       return fail(LOS_ERR_UNSUPPORTED, "los_project: the E-mode kernel is FP64 only");
-    return project_mixed(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S, nsrc,
-                         prec, (float *)delta, (hipStream_t)stream);
+    const char *fz = std::getenv("LOS_MIXED_FUSED");
+    if (fz && std::atoi(fz) == 0)
+      return project_mixed(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S,
+                           nsrc, prec, (float *)delta, (hipStream_t)stream);
+    return project_mixed_fused(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S,
+                               nsrc, prec, (float *)delta, (hipStream_t)stream);
   }
 
   // Default: the single descending sweep; LOS_PROJ_SCHEME=0 selects the

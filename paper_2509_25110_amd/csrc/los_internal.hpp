@@ -108,6 +108,44 @@ hipError_t mfma_gemm_lds_launch(const GemmArgs &a, int kcount, int max_ncol, hip
 hipError_t mfma_gemm_launch(const GemmArgs &a, int prec, const GemmTile &t, int kcount,
                             int max_ncol, hipStream_t s);
 
+// Projection product with the Bessel tiles regenerated in LDS from FP64 seeds
+// (project_fused.hip).  Rows of a chunk as for GemmArgs (k0, row_index for
+// the k value, col_cnt / col_off / s_* / dtrans / delta for S and the
+// output).  Workspace per chunk row: seeds at every 32-row segment top,
+// 1/x and the top row R of every node (fused_workspace_at).
+struct FusedArgs {
+  int lmin, lmax, nl, nlb, nseg;   // nseg = segments of 32 rows covering 16 * nlb rows
+  int64_t ntau, ntp;               // ntp: nodes padded to a multiple of 64
+  int64_t k0;
+  const int64_t *row_index;        // chunk row -> k index (device) or nullptr (k0 + kc)
+  double tau0;
+  const double *k, *tau, *w;
+  double2 *seed;                   // [kcount][nseg][ntp]
+  double *nix;                     // [kcount][ntp]
+  int *rtop;                       // [kcount][ntp]
+  const float *S;
+  int64_t s_kstride, s_cstride;
+  int ncol;
+  const int *col_cnt;
+  const int64_t *col_off;
+  int64_t col_base;
+  const int *col_lmax;
+  int dtrans;
+  float *delta;
+};
+struct FusedShape {
+  int tm, tn;  // l rows x columns per workgroup
+};
+// Compiled shapes: 0 256x128 (waves 4x2), 1 128x128 (2x2), 2 256x128 (2x4),
+// 3 256x256 (2x4), 4 256x16 (8x1), 5 128x16 (4x1).
+constexpr int kFusedShapeCount = 6;
+FusedShape fused_shape_at(int i);
+size_t fused_seed_bytes_per_row(int nseg, int64_t ntp);
+void fused_workspace_at(FusedArgs &a, void *ws, int kcount);
+hipError_t jseed_launch(const FusedArgs &a, int kcount, hipStream_t s);
+hipError_t fused_gemm_launch(const FusedArgs &a, int prec, int shape, int kcount, int max_ncol,
+                             hipStream_t s);
+
 // Per-model C_l of a batch, one chunk of master rows at a time (batch_cl.hip).
 // D is the chunk's transposed product: D[(packed column - col_base) * nl + l - lmin].
 struct BatchClArgs {

@@ -36,7 +36,8 @@ EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
            "los_bessel_table", "los_project", "los_project_kernels", "cl_integrate",
            "los_spline_sources", "los_interp_sources", "los_project_lsample", "los_cl_interp",
            "los_batch_create",
-           "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_destroy",
+           "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_solve_timed",
+           "los_batch_destroy",
            "emu_create", "emu_destroy", "emu_nparams", "emu_get_params", "emu_set_params",
            "emu_get_pca", "emu_set_pca", "emu_forward", "emu_loss_grad", "emu_fit", "emu_train",
            "emu_infer")
@@ -91,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.los_batch_info.argtypes = [vp, vp]
     lib.los_batch_solve.restype = ctypes.c_int
     lib.los_batch_solve.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.los_batch_solve_timed.restype = ctypes.c_int
+    lib.los_batch_solve_timed.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.los_batch_destroy.restype = None
     lib.los_batch_destroy.argtypes = [vp]
     u64 = ctypes.c_uint64
@@ -460,10 +463,10 @@ class Batch:
 
     def los_batch_info(self) -> dict:
         import numpy as np
-        info = np.zeros(8, dtype=np.int32)
+        info = np.zeros(10, dtype=np.int32)
         _check(lib().los_batch_info(self._h, info.ctypes.data))
         keys = ("tile_mb", "tile_nc", "rows_per_chunk", "chunks", "rows", "lmax", "tuned",
-                "graph")
+                "graph", "fused", "fused_shape")
         return {k: int(v) for k, v in zip(keys, info)}
 
     def los_batch_solve(self, tau0: float, k_master: torch.Tensor, tau: torch.Tensor,
@@ -487,6 +490,27 @@ class Batch:
                                      _ptr(S_packed), _ptr(w_lnk), _ptr(Pk), _ptr(cl),
                                      _stream(stream)))
         return cl
+
+    def los_batch_solve_timed(self, tau0: float, k_master: torch.Tensor, tau: torch.Tensor,
+                              w_tau: torch.Tensor, S_packed: torch.Tensor, w_lnk: torch.Tensor,
+                              Pk: torch.Tensor, cl: torch.Tensor, stream=None) -> dict:
+        """Eager instrumented solve into `cl`; returns the summed device milliseconds and launch
+        counts of the Bessel, product and C_l kernels."""
+        import numpy as np
+        npos = int(self._koff[-1])
+        _need(w_lnk, torch.float64, npos, "w_lnk")
+        _need(Pk, torch.float64, npos, "Pk")
+        _need(cl, torch.float64, self.nmodels * self.npairs * (self.lmax_max - 1), "cl")
+        if S_packed.dtype != torch.float32 or S_packed.numel() % self.ntau:
+            raise ValueError("S_packed must be float32 [ncols, ntau]")
+        ms = np.zeros(3, dtype=np.float64)
+        n = np.zeros(3, dtype=np.int32)
+        _check(lib().los_batch_solve_timed(self._h, float(tau0), _ptr(k_master), _ptr(tau),
+                                           _ptr(w_tau), _ptr(S_packed), _ptr(w_lnk), _ptr(Pk),
+                                           _ptr(cl), ms.ctypes.data, n.ctypes.data,
+                                           _stream(stream)))
+        return {"bessel_ms": float(ms[0]), "product_ms": float(ms[1]), "cl_ms": float(ms[2]),
+                "launches": int(n[1])}
 
     def los_batch_destroy(self):
         if self._h is not None and self._h.value:

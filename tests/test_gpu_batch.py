@@ -119,6 +119,7 @@ def test_batch_graph_replays_match_eager(torch_dev, ctx, monkeypatch):
 
 @pytest.mark.parametrize("mb,nc", [(1, 1), (4, 1), (2, 4), (4, 4), (16, 8)])
 def test_batch_tiles_agree(torch_dev, ctx, mb, nc, monkeypatch):
+    monkeypatch.setenv("LOS_BATCH_FUSED", "0")
     b = small_batch(seed=13)
     monkeypatch.setenv("LOS_BATCH_TILE_MB", "2")
     monkeypatch.setenv("LOS_BATCH_TILE_NC", "2")
@@ -133,8 +134,68 @@ def test_batch_tiles_agree(torch_dev, ctx, mb, nc, monkeypatch):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_batch_fused_matches_tables(torch_dev, ctx, prec, monkeypatch):
+    """The default pipeline (Bessel tiles regenerated in LDS) gives bitwise the C_l of the table
+    pipeline (same values, same accumulation order; both one chunk here), for every wide fused
+    tile shape."""
+    b = small_batch(n=9, seed=23, lmax_range=(100, 700), nk_range=(40, 200), master_nk=300,
+                    master_kmax=0.12, ntau=900)
+    monkeypatch.setenv("LOS_BATCH_FUSED", "0")
+    monkeypatch.setenv("LOS_BATCH_TILE_MB", "2")
+    monkeypatch.setenv("LOS_BATCH_TILE_NC", "4")
+    plan, S, base = solve(torch_dev, ctx, b, prec)
+    assert plan.los_batch_info()["fused"] == 0
+    plan.close()
+    monkeypatch.delenv("LOS_BATCH_FUSED")
+    for shape in range(4):
+        monkeypatch.setenv("LOS_BATCH_SHAPE", str(shape))
+        plan, _, cl = solve(torch_dev, ctx, b, prec, S=S)
+        info = plan.los_batch_info()
+        assert info["fused"] == 1 and info["fused_shape"] == shape and info["chunks"] == 1
+        np.testing.assert_array_equal(cl, base)
+        plan.close()
+
+
+def test_batch_fused_autotuned_vs_oracle(torch_dev, ctx):
+    """The fused pipeline with its autotuned shape, on a batch whose rows span several l tiles,
+    column tiles and 64-node chunks, against the oracle per model."""
+    b = small_batch(n=12, seed=29, lmax_range=(200, 900), nk_range=(50, 160), master_nk=200,
+                    master_kmax=0.15, ntau=1100)
+    plan, S, cl = solve(torch_dev, ctx, b, 1)
+    info = plan.los_batch_info()
+    assert info["fused"] == 1 and info["tuned"] == 1
+    col, _ = plan.los_batch_columns()
+    S32 = S.cpu().numpy()
+    for m in range(b.nmodels):
+        L = int(b.lmax[m])
+        cref, CA = oracle_model(b, m, col, S32)
+        bound = np.maximum(1e-4 * np.abs(cref), 2.2 * eps_for(1, b.ntau) * CA)
+        worst = float(np.max(np.abs(cl[m, :, :L - 1] - cref) / bound))
+        assert worst <= 1.0, (m, worst)
+        assert np.all(cl[m, :, L - 1:] == 0.0), m
+    plan.close()
+
+
+def test_batch_fused_chunking(torch_dev, ctx, monkeypatch):
+    """The fused pipeline with a workspace of a few rows per chunk (many chunks) matches one
+    chunk to rounding of the k sum."""
+    b = small_batch(seed=31)
+    plan, S, base = solve(torch_dev, ctx, b, 1)
+    assert plan.los_batch_info()["chunks"] == 1
+    plan.close()
+    monkeypatch.setenv("LOS_BATCH_MIB", "1")
+    plan, _, cl = solve(torch_dev, ctx, b, 1, S=S)
+    assert plan.los_batch_info()["chunks"] >= 4
+    scale = np.maximum(np.abs(base), 1e-300)
+    assert np.max(np.abs(cl - base) / scale) <= 1e-12
+    plan.close()
+
+
 def test_batch_chunking(torch_dev, ctx, monkeypatch):
-    """A workspace of one Bessel table per chunk (many chunks) matches one chunk to rounding."""
+    """Table pipeline: a workspace of one Bessel table per chunk (many chunks) matches one
+    chunk to rounding."""
+    monkeypatch.setenv("LOS_BATCH_FUSED", "0")
     b = small_batch(seed=17)
     plan, S, base = solve(torch_dev, ctx, b, 1)
     assert plan.los_batch_info()["chunks"] == 1
@@ -178,23 +239,31 @@ def test_batch_invalid_arguments(torch_dev, ctx):
         ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs, prec=0)
 
 
-def test_c4_full_size_sampled(torch_dev, ctx):
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_c4_full_size(torch_dev, ctx, prec):
     """The 256-model batch (l_max in [1500, 5000], 2000..8000 k of the 8000-point master grid,
-    3000 tau) in the configuration bench.py times: the C_l of the golden models within 1e-4 of
-    the FP64 oracle."""
+    3000 tau) in the configuration bench.py times (autotuned fused pipeline, graph replay):
+    every C_l of the 8 seeded golden models within 1e-4 of the FP64 oracle (TE relative to
+    sqrt(TT EE)), and nothing written beyond each model's l_max."""
     torch = torch_dev
     b = inputs.batch_inputs(inputs.draw_models(256))
     plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
-                                prec=2)
+                                prec=prec)
     col, ncols = plan.los_batch_columns()
     S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
     inputs.batch_sources_device(b, col, S, torch)
-    _, _, cl = solve(torch, ctx, b, 2, S=S, plan=plan)
+    _, _, cl = solve(torch, ctx, b, prec, S=S, plan=plan)
     assert np.all(np.isfinite(cl))
+    info = plan.los_batch_info()
+    assert info["fused"] == 1 and info["graph"] == 1
     gold = np.loadtxt(GOLDEN_C4)
+    models = np.unique(gold[:, 0]).astype(int)
+    assert models.size == 8
     worst = 0.0
-    for m in np.unique(gold[:, 0]).astype(int):
+    for m in models:
         g = gold[gold[:, 0] == m]
+        L = int(b.lmax[m])
+        assert g.shape[0] == L - 1                       # every multipole of the model
         ls = g[:, 1].astype(int) - 2
         ref = g[:, 2:].T
         got = cl[m][:, ls]
@@ -205,6 +274,9 @@ def test_c4_full_size_sampled(torch_dev, ctx):
                 rel = np.abs(got[p] - ref[p]) / np.sqrt(ref[b.pairs.index((a, a))] *
                                                         ref[b.pairs.index((c, c))])
             worst = max(worst, float(np.max(rel)))
-    print("C4 batch: max C_l rel err vs oracle %.3e (models %s)" % (worst, np.unique(gold[:, 0])))
+        assert np.all(cl[m, :, L - 1:] == 0.0), m
+    print("C4 batch prec %d: max C_l rel err vs oracle %.3e (models %s, shape %d)"
+          % (prec, worst, models, info["fused_shape"]))
     assert worst <= 1e-4
+    del S
     plan.close()

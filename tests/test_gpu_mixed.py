@@ -108,13 +108,43 @@ def test_mixed_small_vs_oracle(torch_dev, ctx, cfg, prec):
 
 @pytest.mark.parametrize("mb,nc", [(1, 1), (2, 1), (2, 2), (4, 4), (16, 8)])
 def test_mixed_tiles_agree(torch_dev, ctx, mb, nc, monkeypatch):
-    """Every compiled tile shape, including the LDS-staged 256 x 128 kernel, gives the same
-    Delta (bitwise: the tau order of the accumulation does not depend on the tile)."""
+    """Table pipeline: every compiled tile shape, including the LDS-staged 256 x 128 kernel,
+    gives the same Delta (bitwise: the tau order of the accumulation does not depend on the
+    tile)."""
+    monkeypatch.setenv("LOS_MIXED_FUSED", "0")
     wl = inputs.small(lmax=150, nk=6, kmax=0.05, ntau=700, nsrc=3)
     base, _, _ = run_mixed(torch_dev, ctx, wl, 2)
     monkeypatch.setenv("LOS_GEMM_MB", str(mb))
     monkeypatch.setenv("LOS_GEMM_NC", str(nc))
     d, _, _ = run_mixed(torch_dev, ctx, wl, 2)
+    np.testing.assert_array_equal(d, base)
+
+
+FUSED_CASES = [
+    dict(lmax=150, nk=6, kmax=0.05, ntau=700, nsrc=3),
+    dict(lmax=61, nk=12, kmax=0.02, ntau=300, nsrc=3),              # ragged l, one tile
+    dict(lmax=333, nk=9, kmax=0.1, ntau=2500, nsrc=3),              # several l tiles, 40 chunks
+    dict(lmax=90, nk=7, kmax=0.2, ntau=190, nsrc=1, kmin=0.01),     # x >> lmax, ragged tau
+    dict(lmax=600, nk=4, kmax=0.06, ntau=1003, nsrc=2),             # ntau not a multiple of 4
+]
+
+
+@pytest.mark.parametrize("prec", list(PRECS), ids=list(PRECS))
+@pytest.mark.parametrize("shape", [4, 5, 0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", FUSED_CASES, ids=[str(i) for i in range(len(FUSED_CASES))])
+def test_mixed_fused_matches_tables(torch_dev, ctx, cfg, shape, prec, monkeypatch):
+    """The default pipeline (Bessel tiles regenerated in LDS from seeds every 32 multipoles)
+    gives bitwise the Delta of the table pipeline (whole FP32 tables, fragment product): the
+    same recurrence cadence and the same accumulation order, for every tile shape."""
+    p = PRECS[prec]
+    wl = inputs.small(**cfg)
+    monkeypatch.setenv("LOS_MIXED_FUSED", "0")
+    monkeypatch.setenv("LOS_GEMM_MB", "2")
+    monkeypatch.setenv("LOS_GEMM_NC", "1")
+    base, _, _ = run_mixed(torch_dev, ctx, wl, p)
+    monkeypatch.delenv("LOS_MIXED_FUSED")
+    monkeypatch.setenv("LOS_FUSED_SHAPE", str(shape))
+    d, _, _ = run_mixed(torch_dev, ctx, wl, p)
     np.testing.assert_array_equal(d, base)
 
 

@@ -72,13 +72,34 @@ def assert_cl(c, cref, pairs, tol=1e-10):
         assert np.max(rel) <= tol, ("C_l", p, float(np.max(rel)), int(np.argmax(rel)))
 
 
+def cl_bound_from_delta(ref, A, wl, tol, cut_floor):
+    """First-order propagation of the normwise Delta allowance to C_l: with
+    E = tol * max_k A (per l, source) + cut_floor * max_l A (per k, source) the allowed
+    |Delta - Delta_ref| and |Delta_ref| <= A,
+      |C - C_ref| <= 4 pi sum_k w P (E_a A_b + A_a E_b + E_a E_b)   per pair and l."""
+    E = tol * np.max(A, axis=0, keepdims=True) + cut_floor * np.max(A, axis=1, keepdims=True)
+    wp = (4.0 * np.pi * wl.w_lnk * wl.Pk)[:, None]
+    out = np.empty((len(wl.pairs), wl.nl))
+    for p, (a, b) in enumerate(wl.pairs):
+        out[p] = np.sum(wp * (E[:, :, a] * A[:, :, b] + A[:, :, a] * E[:, :, b] +
+                              E[:, :, a] * E[:, :, b]), axis=0)
+    return out
+
+
 def check_workload(torch, ctx, wl, tol=1e-10, cut_floor=0.0):
     d, c = run_gpu(torch, ctx, wl)
     ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S, with_abs=True)
     assert np.all(np.isfinite(d))
     assert_delta_normwise(d, ref, A, tol, cut_floor)
+    cref = oracle.cl(ref, wl.w_lnk, wl.Pk, wl.pairs)
     if cut_floor == 0.0:
-        assert_cl(c, oracle.cl(ref, wl.w_lnk, wl.Pk, wl.pairs), list(wl.pairs), tol)
+        assert_cl(c, cref, list(wl.pairs), tol)
+    else:
+        # where the band cut decides an entry, C_l is held to the propagated Delta allowance
+        bound = np.maximum(tol * np.abs(cref),
+                           1.01 * cl_bound_from_delta(ref, A, wl, tol, cut_floor))
+        worst = float(np.max(np.abs(c - cref) / np.maximum(bound, 1e-300)))
+        assert worst <= 1.0, ("C_l vs propagated bound", worst)
     return d, c
 
 
@@ -135,7 +156,8 @@ def test_project_small_vs_oracle(torch_dev, ctx, cfg):
 def test_project_evanescent_columns(torch_dev, ctx):
     """x <= 14 for every node, l up to 50: the lensing column at l > ~35 lies in the evanescent
     tail for all k (|Delta| ~ 1e-27).  There the GPU's band cut is the error; it stays below
-    1e-18 of each row's largest entry."""
+    1e-18 of each row's largest entry, and C_l stays within that allowance propagated to the
+    k sum (and within 1e-10 relative wherever the cut does not decide the value)."""
     wl = inputs.small(lmax=50, nk=5, kmax=1e-3, ntau=64, nsrc=3)
     check_workload(torch_dev, ctx, wl, cut_floor=1e-18)
 
@@ -214,37 +236,50 @@ def test_cl_integrate_vs_oracle(torch_dev, ctx):
 
 # ---------------------------------------------------------------- full benchmark size
 
-def test_c2_full_size_sampled(torch_dev, ctx):
-    """The benchmark workload (C2: l = 2..2500, 4000 k, 3000 tau, T/E/lensing) in the launch
-    configuration bench.py times: C_l at the golden multipoles, Delta at sampled k rows."""
-    torch = torch_dev
-    wl = inputs.config("C2")
+def full_size_check(torch, ctx, name, golden, rows):
+    """A full-size FP64 workload in the launch configuration bench.py times: C_l at every l
+    against the oracle's golden file (1e-10 relative, TE relative to sqrt(TT EE)), and Delta
+    at the sampled k rows normwise (1e-10 of the per-(l, source) scale over those rows)."""
+    wl = inputs.config(name)
     d, c = run_gpu(torch, ctx, wl)
     assert np.all(np.isfinite(d)) and np.all(np.isfinite(c))
-    gold = np.loadtxt(GOLDEN)
+    gold = np.loadtxt(golden)
+    assert gold.shape[0] == wl.nl      # every multipole
     ls = gold[:, 0].astype(int)
-    cref = np.zeros((4, wl.nl))
-    cref[:, ls - wl.lmin] = gold[:, 1:].T
     cs = c[:, ls - wl.lmin]
-    cg = cref[:, ls - wl.lmin]
+    cg = gold[:, 1:].T
     for p, (a, b) in enumerate(wl.pairs):
         if a == b:
             rel = np.abs(cs[p] / cg[p] - 1)
         else:
             rel = np.abs(cs[p] - cg[p]) / np.sqrt(cg[a] * cg[b])
         assert np.max(rel) <= 1e-10, (wl.pair_names[p], float(np.max(rel)), ls[np.argmax(rel)])
-    rows = [0, 1, 700, 1999, 2600, 3100, 3500, 3800, 3998, 3999]
     refs, As = [], []
     for r in rows:
         ref, A = oracle.project(wl.lmin, wl.lmax, wl.k, wl.tau, wl.tau0, wl.w_tau, wl.S,
                                 with_abs=True, k_range=(r, r + 1))
         refs.append(ref[0])
         As.append(A[0])
-    # per (l, source) scale over the sampled rows: a lower bound of the max over all k
     scale = np.maximum(np.max(np.stack(As), axis=0), 1e-300)
     for r, ref in zip(rows, refs):
         err = np.max(np.abs(d[r] - ref) / scale)
         assert err <= 1e-10, (r, err)
+
+
+def test_c3_full_size_fp64(torch_dev, ctx):
+    """The mixed-precision workload's own FP64 plain path (C3: l = 2..5000, 8000 k, 4000 tau,
+    T/E/lensing; launch shape 4 waves x 16 slots with the 2-block ring): every C_l within 1e-10
+    of the oracle, Delta at sampled k rows normwise within 1e-10."""
+    full_size_check(torch_dev, ctx, "C3",
+                    os.path.join(os.path.dirname(GOLDEN), "c3_cl_oracle.txt"),
+                    [0, 1, 3000, 5200, 6400, 7100, 7600, 7998, 7999])
+
+
+def test_c2_full_size_sampled(torch_dev, ctx):
+    """The benchmark workload (C2: l = 2..2500, 4000 k, 3000 tau, T/E/lensing) in the launch
+    configuration bench.py times: C_l at every l, Delta at sampled k rows."""
+    full_size_check(torch_dev, ctx, "C2", GOLDEN,
+                    [0, 1, 700, 1999, 2600, 3100, 3500, 3800, 3998, 3999])
 
 
 # ---------------------------------------------------------------- two-pass kernel

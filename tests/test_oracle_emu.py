@@ -70,6 +70,47 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-15)
 
 
+def test_adam_constant_gradient_three_steps():
+    """With the same gradient at every step, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so
+    the bias-corrected moments are exactly g and g^2 at every t and each step moves theta by
+    -lr g / (|g| + eps).  A wrong correction exponent at t >= 2 breaks this."""
+    g = np.array([3.0, -0.5, 2.0 ** -10, 7.25])
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in (1, 2, 3):
+        th, m, v = eo.adam_step(th, g, m, v, t, lr=0.01)
+        np.testing.assert_allclose(m, (1 - 0.9 ** t) * g, rtol=1e-15)
+        np.testing.assert_allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+        np.testing.assert_allclose(th, -0.01 * t * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_adam_two_steps_hand_computed():
+    """Adam (Kingma and Ba, Algorithm 1) for one parameter, gradients 1 then -2, lr 0.1,
+    carried out in exact rational arithmetic for the moments and their bias corrections (the
+    oracle's FP64 evaluation agrees to rounding; a wrong bias-correction power moves theta by
+    more than 1e-2):
+      t=1: m = 1/10, v = 1/1000, mhat = 1, vhat = 1;
+      t=2: m = -11/100, v = 4999/1000000, mhat = -11/19, vhat = 4999/1999."""
+    from fractions import Fraction as F
+    b1, b2 = F(9, 10), F(999, 1000)
+    m1, v1 = (1 - b1) * 1, (1 - b2) * 1
+    m2, v2 = b1 * m1 + (1 - b1) * (-2), b2 * v1 + (1 - b2) * 4
+    assert (m2, v2) == (F(-11, 100), F(4999, 1000000))
+    mh2, vh2 = m2 / (1 - b1 ** 2), v2 / (1 - b2 ** 2)
+    assert (mh2, vh2) == (F(-11, 19), F(4999, 1999))
+    th1 = -0.1 * 1.0 / (1.0 + 1e-8)
+    th2 = th1 - 0.1 * float(mh2) / (np.sqrt(float(vh2)) + 1e-8)
+    th, m, v = eo.adam_step(np.zeros(1), np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr=0.1)
+    assert abs(th[0] - th1) <= 1e-16
+    th, m, v = eo.adam_step(th, np.array([-2.0]), m, v, 2, lr=0.1)
+    assert abs(m[0] - float(m2)) <= 1e-15 and abs(v[0] - float(v2)) <= 1e-15
+    assert abs(th[0] - th2) <= 1e-13, (th[0], th2)
+    # the third step with gradient 0.5 continues the same recursion
+    m3, v3 = b1 * m2 + (1 - b1) * F(1, 2), b2 * v2 + (1 - b2) * F(1, 4)
+    th3 = th2 - 0.1 * float(m3 / (1 - b1 ** 3)) / (np.sqrt(float(v3 / (1 - b2 ** 3))) + 1e-8)
+    th, m, v = eo.adam_step(th, np.array([0.5]), m, v, 3, lr=0.1)
+    assert abs(th[0] - th3) <= 1e-13, (th[0], th3)
+
+
 def test_pca_truncation_floor_and_svd():
     rng = np.random.default_rng(5)
     n, nl, k = 300, 40, 6
