@@ -15,6 +15,8 @@ integrals) and Sec. 3.2 / Algorithm 1 (loop over k, then l, then tau):
 * :func:`project`       -- Delta^X_l(k_i) = sum_n w_n S_X(k_i, tau_n) K_l(k_i (tau0 - tau_n)),
                            K = j_l, or eps_l for the sources selected by a mask
 * :func:`cl`            -- C^XY_l = 4 pi sum_i w_i P(k_i) Delta^X_l(k_i) Delta^Y_l(k_i)
+* :func:`tensor_kernels` -- the tensor-mode kernels K^T, K^E, K^B of the line-of-sight method
+* :func:`project_tensor` -- the tensor transfer functions Delta^T, Delta^E, Delta^B
 """
 from __future__ import annotations
 
@@ -87,9 +89,15 @@ def _load():
                                       _c_double_p, _c_double_p, _c_int32_p, ctypes.c_int32,
                                       _c_double_p]
             lib.oracle_num_threads.argtypes = []
+            lib.oracle_tensor_kernels.argtypes = [ctypes.c_int32, ctypes.c_double, _c_double_p,
+                                                  _c_double_p, _c_double_p, _c_double_p]
+            lib.oracle_project_tensor.argtypes = [
+                ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p]
             for f in (lib.oracle_sph_jl, lib.oracle_bessel_table, lib.oracle_project,
                       lib.oracle_project_kernels, lib.oracle_eps_l, lib.oracle_cl,
-                      lib.oracle_num_threads):
+                      lib.oracle_num_threads, lib.oracle_tensor_kernels,
+                      lib.oracle_project_tensor):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -180,3 +188,43 @@ def cl(delta, w_lnk, Pk, pairs) -> np.ndarray:
                            out.ctypes.data_as(_c_double_p))
     _check(rc, "cl")
     return out
+
+
+def tensor_kernels(lmax, x):
+    """Tensor-mode kernels at one x for l = 0..lmax: (K^T, K^E, K^B) with
+    K^T = sqrt((l+2)!/(l-2)!) j_l/x^2, K^E = -j_l + j_l'' + 2 j_l/x^2 + 4 j_l'/x,
+    K^B = 2 j_l' + 4 j_l/x (the published tensor line-of-sight kernels of the method the
+    paper cites in Sec. 2.1); 0 for l < 2."""
+    jl, kt, ke, kb = (np.empty(lmax + 1) for _ in range(4))
+    _check(_load().oracle_tensor_kernels(int(lmax), float(x), jl.ctypes.data_as(_c_double_p),
+                                         kt.ctypes.data_as(_c_double_p),
+                                         ke.ctypes.data_as(_c_double_p),
+                                         kb.ctypes.data_as(_c_double_p)), "tensor_kernels")
+    return kt, ke, kb
+
+
+def project_tensor(lmin, lmax, k, tau, tau0, w_tau, S, with_abs=False, k_range=None):
+    """Tensor transfer functions: ``S`` is [2, nk, ntau] (S_T, S_P); returns delta
+    [nk, nl, 3] with the T, E and B transfer functions (and, if ``with_abs``, the scale
+    sum_n |w S| times the absolute sum of each kernel's terms, same shape).  lmin >= 2."""
+    S = np.asarray(S)
+    k = np.asarray(k)
+    if k_range is not None:
+        a, b = k_range
+        k = k[a:b]
+        S = S[:, a:b, :]
+    k, kp = _f64(k)
+    tau, tp = _f64(tau)
+    w_tau, wp = _f64(w_tau)
+    S, sp = _f64(S)
+    nsrc, nk, ntau = S.shape
+    assert nsrc == 2 and nk == k.size and ntau == tau.size == w_tau.size
+    nl = lmax - lmin + 1
+    delta = np.empty((nk, nl, 3))
+    absd = np.empty((nk, nl, 3)) if with_abs else None
+    rc = _load().oracle_project_tensor(
+        int(lmin), int(lmax), nk, ntau, float(tau0), kp, tp, wp, sp,
+        delta.ctypes.data_as(_c_double_p),
+        absd.ctypes.data_as(_c_double_p) if with_abs else None)
+    _check(rc, "project_tensor")
+    return (delta, absd) if with_abs else delta

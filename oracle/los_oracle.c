@@ -296,6 +296,161 @@ int oracle_project_kernels(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
     return bad;
 }
 
+/*
+ * Tensor (gravitational-wave) radial kernels of the line-of-sight method in
+ * flat space.  Sec. 2.1 of the gCAMB paper states that tensor perturbations
+ * and B modes give equations of the same kind as Eq. 2-3 and cites Seljak &
+ * Zaldarriaga (1996) for the method; the kernels are those published for it
+ * (Seljak & Zaldarriaga 1996; Zaldarriaga & Seljak 1997, tensor modes):
+ *
+ *   K^T_l(x) = sqrt((l+2)!/(l-2)!) j_l(x) / x^2
+ *   K^E_l(x) = -j_l(x) + j_l''(x) + 2 j_l(x) / x^2 + 4 j_l'(x) / x
+ *   K^B_l(x) = 2 j_l'(x) + 4 j_l(x) / x
+ *
+ * with the derivatives written out from their textbook definitions
+ * (DLMF 10.51.2 and the differential equation DLMF 10.47.1):
+ *   j_l'  = j_{l-1} - (l+1) j_l / x
+ *   j_l'' = -(2/x) j_l' - (1 - l(l+1)/x^2) j_l.
+ * For l < 2 every kernel is set to 0 (the spin-2 projection starts at l = 2).
+ * At x -> 0 (x < 1e-150, where 1/x^2 would overflow) the power series
+ * j_l ~ x^l/(2l+1)!! gives K^T_2 -> sqrt(24)/15, K^E_2 -> 2/15 + 2/15 + 8/15
+ * = 4/5, and 0 for K^B_2 and for every kernel at l >= 3.
+ * jl is scratch for j_l (lmax + 1 values); kt, ke, kb receive l = 0..lmax.
+ */
+static void tensor_from_jl(int32_t lmax, double x, const double *jl, double *kt, double *ke,
+                           double *kb)
+{
+    for (int32_t l = 0; l <= lmax; ++l) {
+        kt[l] = 0.0;
+        ke[l] = 0.0;
+        kb[l] = 0.0;
+    }
+    if (x < 1e-150) {
+        if (lmax >= 2) {
+            kt[2] = sqrt(24.0) / 15.0;
+            ke[2] = 4.0 / 5.0;
+        }
+        return;
+    }
+    const double ix = 1.0 / x;
+    const double ix2 = ix * ix;
+    for (int32_t l = 2; l <= lmax; ++l) {
+        const double j = jl[l];
+        const double jp = jl[l - 1] - (double)(l + 1) * j * ix;
+        const double jpp = -2.0 * ix * jp - (1.0 - (double)l * (double)(l + 1) * ix2) * j;
+        const double f = (double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2);
+        kt[l] = sqrt(f) * (j * ix2);
+        ke[l] = -j + jpp + 2.0 * j * ix2 + 4.0 * jp * ix;
+        kb[l] = 2.0 * jp + 4.0 * j * ix;
+    }
+}
+
+/* The three tensor kernels at one x, l = 0..lmax (jl: scratch of lmax + 1). */
+int oracle_tensor_kernels(int32_t lmax, double x, double *jl, double *kt, double *ke, double *kb)
+{
+    if (lmax < 0 || !(x >= 0.0) || !isfinite(x) || jl == NULL || kt == NULL || ke == NULL ||
+        kb == NULL)
+        return OR_ERR_INVALID;
+    const unsigned fpm = fp_enter();
+    int rc = sph_jl_body(lmax, x, jl);
+    if (rc == OR_OK)
+        tensor_from_jl(lmax, x, jl, kt, ke, kb);
+    fp_leave(fpm);
+    return rc;
+}
+
+/*
+ * Tensor line-of-sight transfer functions (the tensor analogue of Eq. 2-3):
+ *   delta[(i*nl + l-lmin)*3 + 0] = sum_n w_n S_T(k_i, tau_n) K^T_l(x)
+ *   delta[(i*nl + l-lmin)*3 + 1] = sum_n w_n S_P(k_i, tau_n) K^E_l(x)
+ *   delta[(i*nl + l-lmin)*3 + 2] = sum_n w_n S_P(k_i, tau_n) K^B_l(x)
+ * x = k_i (tau0 - tau_n).  S is [2][nk][ntau] (S_T, then S_P), row-major.
+ * absdelta (optional) receives the sums of |w S| times the sum of the
+ * absolute values of each kernel's terms as written above (for E:
+ * |j| + |j''| + |2j/x^2| + |4j'/x|; for B: |2j'| + |4j/x|; for T: |K^T|),
+ * the scale of a normwise comparison that the cancellation between a
+ * kernel's own terms does not shrink.
+ */
+int oracle_project_tensor(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
+                          const double *k, const double *tau, const double *w_tau,
+                          const double *S, double *delta, double *absdelta)
+{
+    if (lmin < 2 || lmax < lmin || nk < 0 || ntau < 0 || k == NULL || tau == NULL ||
+        w_tau == NULL || S == NULL || delta == NULL)
+        return OR_ERR_INVALID;
+    const int64_t nl = (int64_t)lmax - lmin + 1;
+    int bad = 0;
+#pragma omp parallel
+    {
+        const unsigned fpm = fp_enter();
+        double *buf = (double *)malloc(sizeof(double) * 7 * (size_t)(lmax + 1));
+        if (buf == NULL) {
+#pragma omp atomic write
+            bad = OR_ERR_OOM;
+        }
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nk; ++i) {
+            if (buf == NULL)
+                continue;
+            double *jl = buf, *kt = buf + (lmax + 1), *ke = kt + (lmax + 1), *kb = ke + (lmax + 1);
+            double *at = kb + (lmax + 1), *ae = at + (lmax + 1), *ab = ae + (lmax + 1);
+            double *d = delta + i * nl * 3;
+            double *a = absdelta ? absdelta + i * nl * 3 : NULL;
+            for (int64_t q = 0; q < nl * 3; ++q) {
+                d[q] = 0.0;
+                if (a)
+                    a[q] = 0.0;
+            }
+            for (int64_t n = 0; n < ntau; ++n) {
+                const double chi = tau0 - tau[n];
+                const double x = k[i] * chi;
+                if (sph_jl_body(lmax, x, jl) != OR_OK) {
+#pragma omp atomic write
+                    bad = OR_ERR_INVALID;
+                    continue;
+                }
+                tensor_from_jl(lmax, x, jl, kt, ke, kb);
+                if (a) {
+                    /* absolute term sums of each kernel (see above) */
+                    for (int32_t l = 0; l <= lmax; ++l) {
+                        at[l] = fabs(kt[l]);
+                        ae[l] = fabs(ke[l]);
+                        ab[l] = fabs(kb[l]);
+                    }
+                    if (x >= 1e-150) {
+                        const double ix = 1.0 / x, ix2 = ix * ix;
+                        for (int32_t l = 2; l <= lmax; ++l) {
+                            const double j = jl[l];
+                            const double jp = jl[l - 1] - (double)(l + 1) * j * ix;
+                            const double jpp =
+                                -2.0 * ix * jp - (1.0 - (double)l * (double)(l + 1) * ix2) * j;
+                            ae[l] = fabs(j) + fabs(jpp) + fabs(2.0 * j * ix2) + fabs(4.0 * jp * ix);
+                            ab[l] = fabs(2.0 * jp) + fabs(4.0 * j * ix);
+                        }
+                    }
+                }
+                const double wt = w_tau[n] * S[((int64_t)0 * nk + i) * ntau + n];
+                const double wp = w_tau[n] * S[((int64_t)1 * nk + i) * ntau + n];
+                for (int32_t l = lmin; l <= lmax; ++l) {
+                    double *dl = d + (int64_t)(l - lmin) * 3;
+                    dl[0] += wt * kt[l];
+                    dl[1] += wp * ke[l];
+                    dl[2] += wp * kb[l];
+                    if (a) {
+                        double *al = a + (int64_t)(l - lmin) * 3;
+                        al[0] += fabs(wt) * at[l];
+                        al[1] += fabs(wp) * ae[l];
+                        al[2] += fabs(wp) * ab[l];
+                    }
+                }
+            }
+        }
+        free(buf);
+        fp_leave(fpm);
+    }
+    return bad;
+}
+
 /* Eq. 2-3 with the j_l kernel for every source. */
 int oracle_project(int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
                    const double *k, const double *tau, const double *w_tau, const double *S,
