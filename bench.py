@@ -35,6 +35,11 @@ GOLDEN = {"C2": os.path.join(ROOT, "tests", "golden", "c2_cl_oracle.txt"),
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
+def progress(msg):
+    """One progress line on stderr (the JSON result is the only stdout line)."""
+    print("bench.py: " + msg, file=sys.stderr, flush=True)
+
+
 def tp_and_band_counts(wl, ls=None):
     """Per-launch work counts over all (k, tau) pairs (host-side counting only).
     TP: l in [lmin, lmax] with x = k (tau0 - tau) >= l + 1/2 (the oscillatory, threshold-free set).
@@ -243,6 +248,7 @@ def run_batch(args):
     col, ncols = plan.los_batch_columns()
     S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
     inputs.batch_sources_device(b, col, S, torch)
+    progress("C4 plan and sources ready (%d packed columns)" % ncols)
     tp, dense = batch_tp_counts(b)
     flops = 2.0 * 3 * tp                     # useful flops: 2 per FMA, 3 sources per TP entry
     K = args.steps
@@ -265,6 +271,7 @@ def run_batch(args):
                              "whole_step_frac": flops / (r["ms"] * 1e-3) / 1e12 / peak}}
 
     main = batch_run_prec(plan, b, S, dv, prec_name, K, args.warmup, torch)
+    progress("C4 %s timed: %.2f ms per step" % (prec_name, main["ms"]))
     info = main["info"]
     plan.close()
     msum = summary(main, "bf16x3_mfma" if prec_name == "bf16x3" else "fp32_mfma")
@@ -301,6 +308,7 @@ def run_batch(args):
         plan2 = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
                                      prec=PRECS[other])
         r2 = batch_run_prec(plan2, b, S, dv, other, K, args.warmup, torch)
+        progress("C4 %s timed: %.2f ms per step" % (other, r2["ms"]))
         plan2.close()
         o = summary(r2, "bf16x3_mfma" if other == "bf16x3" else "fp32_mfma")
         o["roofline"]["traffic"] = None
@@ -324,6 +332,7 @@ def run_batch(args):
             del dd
         tp_sub, _ = batch_tp_counts(inputs.batch_inputs([b.draws[i] for i in sample]))
         fp64 = b.nmodels / (tsum * tp / tp_sub)
+        progress("C4 FP64 plain path on models %s: %.3f s" % (sample, tsum))
         out["fp64_plain_path"] = {"value": fp64, "unit": "spectra/s",
                                   "sample": "models %s solved one by one with the FP64 path "
                                             "(%.3f s), scaled to the batch by TP work"
