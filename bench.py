@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "C_ℓ spectra/s and Δ_ℓ(k) GFMA/s vs FP64 plain path at ≤1e-4 rel err"
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 GOLDEN = {"C2": os.path.join(ROOT, "tests", "golden", "c2_cl_oracle.txt"),
-          "C3": os.path.join(ROOT, "tests", "golden", "c3_cl_oracle.txt")}
+          "C3": os.path.join(ROOT, "tests", "golden", "c3_cl_oracle.txt"),
+          "T2": os.path.join(ROOT, "tests", "golden", "t2_cl_oracle.txt")}
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
@@ -95,7 +96,8 @@ def cpu_baseline(wl, stride):
     rows = np.arange(0, wl.nk, stride)
     S = np.ascontiguousarray(wl.S[:, rows, :])
     t0 = time.perf_counter()
-    d = oracle.project(wl.lmin, wl.lmax, wl.k[rows], wl.tau, wl.tau0, wl.w_tau, S)
+    proj = oracle.project_tensor if wl.name == "T2" else oracle.project
+    d = proj(wl.lmin, wl.lmax, wl.k[rows], wl.tau, wl.tau0, wl.w_tau, S)
     oracle.cl(d, wl.w_lnk[rows], wl.Pk[rows], wl.pairs)
     dt = time.perf_counter() - t0
     per_spectrum = dt * wl.nk / rows.size
@@ -515,7 +517,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C4",
-                    help="C4 (default: the 256-model batch), C5 (emulator), C1/C2/C3 (one model)")
+                    help="C4 (default: the 256-model batch), C5 (emulator), C1/C2/C3 (one model), "
+                         "T2 (tensor modes, FP64)")
     ap.add_argument("--prec", default=None, choices=list(PRECS),
                     help="default fp32 for C4, fp64 for C1-C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -560,13 +563,17 @@ def main():
     from paper_2509_25110_amd import inputs, los
 
     torch.cuda.set_device(0)
-    wl = inputs.config(args.config)
+    tensor = args.config == "T2"
+    wl = inputs.tensor_workload() if tensor else inputs.config(args.config)
     prec = PRECS[args.prec or "fp64"]
+    if tensor and (prec != 0 or args.lsample > 0 or args.interp):
+        print("bench.py: the tensor workload runs the FP64 path only", file=sys.stderr)
+        sys.exit(2)
     sdt = np.float64 if prec == 0 else np.float32
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     k, tau, w, S = dv(wl.k), dv(wl.tau), dv(wl.w_tau), dv(wl.S.astype(sdt))
     wk, Pk = dv(wl.w_lnk), dv(wl.Pk)
-    delta = torch.empty((wl.nk, wl.nl, wl.nsrc), dtype=S.dtype, device="cuda")
+    delta = torch.empty((wl.nk, wl.nl, 3 if tensor else wl.nsrc), dtype=S.dtype, device="cuda")
     cl = torch.empty((len(wl.pairs), wl.nl), dtype=torch.float64, device="cuda")
     ctx = los.Context()
     stream = torch.cuda.current_stream()
@@ -591,7 +598,9 @@ def main():
         cls = torch.empty((len(wl.pairs), ls.size), dtype=torch.float64, device="cuda")
 
     def project():
-        if ls is None:
+        if tensor:
+            ctx.los_project_tensor(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, delta=delta)
+        elif ls is None:
             ctx.los_project(wl.lmin, wl.lmax, k, tau, wl.tau0, w, S, prec=prec, delta=delta)
         else:
             ctx.los_project_lsample(wl.lmin, wl.lmax, ls, k, tau, wl.tau0, w, S, delta=delta)
@@ -640,14 +649,15 @@ def main():
     prep_ms = float(np.mean([a.elapsed_time(b[0]) for a, b in zip(evi, ev)]))
     ms_per_step = total_ms / K
 
+    ncol = 4 if tensor else wl.nsrc  # the tensor sweep accumulates 4 columns
     if ls is None:
         tp, band = tp_and_band_counts(wl)
-        flops = tp * (3.0 + 2.0 * wl.nsrc)  # recurrence FMA + coefficient add, nsrc FMAs, per TP entry
+        flops = tp * (3.0 + 2.0 * ncol)  # recurrence FMA + coefficient add, ncol FMAs, per TP entry
     else:  # the recurrence at every TP entry, the accumulation at the sampled ones
         tp, band, tps = tp_and_band_counts(wl, ls)
         flops = tp * 3.0 + tps * 2.0 * wl.nsrc
     achieved = flops / (proj_ms * 1e-3) / 1e12
-    gfma = wl.nsrc * tp / (ms_per_step * 1e-3) / 1e9
+    gfma = ncol * tp / (ms_per_step * 1e-3) / 1e9
     err = golden_error(cl.cpu().numpy(), wl)
     lsample = None
     if ls is not None:
@@ -668,7 +678,9 @@ def main():
         err = None  # the golden C_l are for sources given on the LOS grid itself
 
     path = {0: "FP64 plain path", 1: "FP32 MFMA path", 2: "split-BF16x3 MFMA path"}[prec]
-    kernel = fp64_kernel()[0] if prec == 0 else "jtable_kernel + mfma_gemm_kernel"
+    if tensor:
+        path = "FP64 tensor-mode path (sweep of S_P, S_P/x, S_P/x^2, S_T/x^2, row combination)"
+    kernel = fp64_kernel()[0] if prec == 0 else "jseed_kernel + fused_gemm_kernel"
     out = {
         "metric": METRIC,
         "value": K / (total_ms * 1e-3),
@@ -691,7 +703,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic_for(prec, wl) if ls is None else None,
                      "kernel": kernel, "kernel_ms": proj_ms,
-                     "work": ("%d TP (l,k,tau) entries x %d FP64 flops" % (tp, 3 + 2 * wl.nsrc)
+                     "work": ("%d TP (l,k,tau) entries x %d FP64 flops" % (tp, 3 + 2 * ncol)
                               if ls is None else
                               "%d TP entries x 3 + %d sampled TP entries x %d FP64 flops"
                               % (tp, tps, 2 * wl.nsrc))},

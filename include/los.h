@@ -152,6 +152,36 @@ int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, in
                         void *delta, void *stream);
 
 /*
+ * Tensor-mode LOS projection (Sec. 2.1: tensor perturbations and B modes give
+ * equations of the same kind as Eq. 2-3; the radial kernels are the published
+ * tensor kernels of the line-of-sight method the paper builds on):
+ *
+ *   delta[(i * nl + (l - lmin)) * 3 + 0] = sum_n w_n S_T(k_i, tau_n) K^T_l(x)
+ *   delta[(i * nl + (l - lmin)) * 3 + 1] = sum_n w_n S_P(k_i, tau_n) K^E_l(x)
+ *   delta[(i * nl + (l - lmin)) * 3 + 2] = sum_n w_n S_P(k_i, tau_n) K^B_l(x)
+ *
+ *   K^T_l = sqrt((l+2)!/(l-2)!) j_l / x^2
+ *   K^E_l = -j_l + j_l'' + 2 j_l / x^2 + 4 j_l' / x
+ *   K^B_l = 2 j_l' + 4 j_l / x,        x = k_i (tau0 - tau_n),
+ *
+ * with the x -> 0 limits K^T_2 = sqrt(24)/15, K^E_2 = 4/5 and 0 otherwise.
+ * S: device, 2*nk*ntau doubles, S[(0 * nk + i) * ntau + n] = S_T and
+ * S[(1 * nk + i) * ntau + n] = S_P.  delta: device, nk*nl*3 doubles (T, E, B).
+ * k, tau, w_tau, tau0 and the limits as for los_project (FP64 only).
+ * Computed as one FP64 sweep of the rows lmin-1 .. lmax over the columns
+ * S_P, S_P/x, S_P/x^2, S_T/x^2, then a combination of neighbouring rows
+ * (j_l' and j_l'' written through j_{l-1}, j_l); the intermediate
+ * nk*(nl+1)*4 doubles live in the context workspace.  The spectra follow from
+ * cl_integrate on delta with nsrc = 3 (pairs over T, E, B).
+ * Errors: LOS_ERR_INVALID for NULL pointers or bad sizes; LOS_ERR_OOM if the
+ * workspace cannot be allocated; LOS_ERR_UNSUPPORTED with the two-pass FP64
+ * scheme (LOS_PROJ_SCHEME=0).
+ */
+int los_project_tensor(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
+                       double tau0, const double *k, const double *tau, const double *w_tau,
+                       const double *S, double *delta, void *stream);
+
+/*
  * Angular power spectra, Eq. 1 with the ln k quadrature written out:
  *
  *   cl[p * nl + l'] = 4 pi sum_i w_lnk[i] * Pk[i]

@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblos.so")
 
 SOURCES = ["los_api.cpp", "bessel_table.hip", "project_fp64.hip", "project_fp64_desc.hip", "cl_reduce.hip", "jtable.hip",
-           "project_mfma.hip", "project_mfma_lds.hip", "project_fused.hip", "batch_cl.hip", "batch_api.cpp", "spline.hip", "cl_interp.hip", "emu_kernels.hip", "emu_api.cpp"]
+           "project_mfma.hip", "project_mfma_lds.hip", "project_fused.hip", "batch_cl.hip", "batch_api.cpp", "spline.hip", "cl_interp.hip", "tensor.hip", "emu_kernels.hip", "emu_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

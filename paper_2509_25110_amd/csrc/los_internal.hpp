@@ -19,6 +19,12 @@ struct ProjectArgs {
   const double *S;  // [nsrc][nk][ntau]
   double *delta;    // [nk][nl][nsrc]
   uint32_t emask;   // bit s: source s uses the E-mode kernel eps_l (sweep kernel only)
+  // Sweep kernel only: bit s of x1mask / x2mask scales column s by 1/x / 1/x^2
+  // per node (no row factor); a node below kXTiny then adds its limit, w S / 3
+  // to row 1 (1/x: j_1(x)/x -> 1/3) or w S / 15 to row 2 (1/x^2: j_2(x)/x^2 ->
+  // 1/15).  Column s reads source plane splane[s] of S (default s).
+  uint32_t x1mask = 0, x2mask = 0;
+  int splane[4] = {0, 1, 2, 3};
   // Multipole sampling (sweep kernel, 16-row blocks): when lsel is set, only
   // rows l with lsel[l - lmin] >= 0 are accumulated and stored, at output
   // row lsel[l - lmin] of delta[k][nls][nsrc]; bmask[bi] has bit r set when
@@ -162,6 +168,12 @@ struct BatchClArgs {
 };
 hipError_t fill_zero_launch(double *p, int64_t n, hipStream_t s);
 hipError_t batch_cl_launch(const BatchClArgs &a, hipStream_t s);
+
+// Tensor-mode combination (tensor.hip): d4[k][l - lmin + 1][4] holds the
+// sweep's columns (P0, P1, P2, T2) on rows lmin-1 .. lmax; out[k][l - lmin][3]
+// receives (Delta^T, Delta^E, Delta^B) for l = lmin .. lmax.
+hipError_t tensor_combine_launch(const double *d4, double *out, int lmin, int nl, int64_t nk,
+                                 hipStream_t s);
 
 // Error reporting shared by the C entry points (los_api.cpp).
 int fail(int code, const char *fmt, ...);

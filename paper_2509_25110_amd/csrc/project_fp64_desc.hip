@@ -26,6 +26,10 @@
 // sqrt((l+2)!/(l-2)!) j_l(x) / x^2): their values are scaled by 1/x^2 per node
 // as they are loaded and their output rows by sqrt((l-1) l (l+1) (l+2)); a node
 // with x below kXTiny adds its limit w S sqrt(24)/15 to l = 2 only.
+// Columns of x1mask / x2mask are scaled by 1/x / 1/x^2 per node with no row
+// factor (the tensor-mode projection combines them afterwards); their x -> 0
+// limits go to l = 1 (w S / 3) and l = 2 (w S / 15).  Column s reads source
+// plane splane[s], so one source can feed several columns.
 #include "bessel_dev.hpp"
 #include "fp64_common.hpp"
 #include "los_internal.hpp"
@@ -64,7 +68,9 @@ __device__ __forceinline__ void sweep_slot(double (&acc)[B * NSRC], double &p1, 
   }
 }
 
-template <int NSRC, int T, int B, bool SMP>
+// SC: the kernel variant with per-column scalings (E-mode, 1/x, 1/x^2) and
+// source planes; without it every column s reads plane s unscaled.
+template <int NSRC, int T, int B, bool SMP, bool SC>
 __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   constexpr int NV = B * NSRC;
   const int nblk = (a.nl + B - 1) / B;
@@ -88,7 +94,8 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   const double kk = a.k[ki];
   const double *srow[NSRC];
 #pragma unroll
-  for (int s = 0; s < NSRC; ++s) srow[s] = a.S + ((int64_t)s * a.nk + ki) * a.ntau;
+  for (int s = 0; s < NSRC; ++s)
+    srow[s] = a.S + ((int64_t)(SC ? a.splane[s] : s) * a.nk + ki) * a.ntau;
 
   // ---------------- per-node setup: the pair at the top row ----------------
   double Jn[T], Jc[T];  // w j_{l+1}, w j_l of the current row, per slot
@@ -193,11 +200,18 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   __syncthreads();
   const int top_blk = bnd[0];
 
-  // E-mode limit at x -> 0: j_2(x)/x^2 -> 1/15 (higher l -> 0)
-  double e2[NSRC];
+  // Limits at x -> 0 of the scaled columns (the nodes below kXTiny are not
+  // swept): j_2(x)/x^2 -> 1/15 for E-mode and 1/x^2 columns at l = 2,
+  // j_1(x)/x -> 1/3 for 1/x columns at l = 1; every other row -> 0.  A column
+  // has at most one such row, so one sum per column (added in block 0).
+  const uint32_t m2 = SC ? (a.emask | a.x2mask) : 0u;
+  const uint32_t m1 = SC ? a.x1mask : 0u;
+  const bool lim1 = m1 != 0 && lmin <= 1;
+  const bool lim2 = m2 != 0 && lmin <= 2;
+  double elim[NSRC];
 #pragma unroll
-  for (int s = 0; s < NSRC; ++s) e2[s] = 0.0;
-  if (a.emask != 0 && lmin == 2) {
+  for (int s = 0; s < NSRC; ++s) elim[s] = 0.0;
+  if (lim1 || lim2) {
 #pragma unroll
     for (int j = 0; j < T; ++j) {
       const int n = (w + W * j) * 64 + lane;
@@ -206,8 +220,10 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
         if (x < kXTiny) {
           const double wn = a.w[n];
 #pragma unroll
-          for (int s = 0; s < NSRC; ++s)
-            if ((a.emask >> s) & 1u) e2[s] += wn * srow[s][n] * (1.0 / 15.0);
+          for (int s = 0; s < NSRC; ++s) {
+            if (lim2 && ((m2 >> s) & 1u)) elim[s] += wn * srow[s][n] * (1.0 / 15.0);
+            else if (lim1 && ((m1 >> s) & 1u)) elim[s] += wn * srow[s][n] * (1.0 / 3.0);
+          }
         }
       }
     }
@@ -229,8 +245,8 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
       if (o >= 0) drow[o] = 0.0;
     }
   }
-  // with E-mode limit terms, block 0 is swept even when no node reaches it
-  const int first = (a.emask != 0 && lmin == 2 && top_blk < 0) ? 0 : top_blk;
+  // with limit terms, block 0 is swept even when no node reaches it
+  const int first = ((lim1 || lim2) && top_blk < 0) ? 0 : top_blk;
   // Sources of the fully-live slots come through a ring of 4 register sets:
   // slot j uses ring[j % 4] and is loaded 3 slots ahead.  S does not depend
   // on the row block, so the last slots of a block prefetch the first slots
@@ -266,11 +282,13 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
       asm volatile("" : "+v"(n));
       double(&sv)[NSRC] = ring[j % 4];
       const double ix = ixs[n];
-      if (a.emask != 0) {  // uniform; the ring entry is reloaded before its next use
+      if (SC && (m2 | m1) != 0) {  // uniform; the ring entry is reloaded before its next use
         const double i2 = ix * ix;
 #pragma unroll
-        for (int s = 0; s < NSRC; ++s)
-          if ((a.emask >> s) & 1u) sv[s] *= i2;
+        for (int s = 0; s < NSRC; ++s) {
+          if ((m2 >> s) & 1u) sv[s] *= i2;
+          else if ((m1 >> s) & 1u) sv[s] *= ix;
+        }
       }
       sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ix, sv, top);
     }
@@ -283,18 +301,29 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
       if (!has(pm, j)) continue;
       double sv[NSRC];
       load_s<NSRC>(sv, srow, n, ntau);
-      if (a.emask != 0) {  // uniform
+      if (SC && (m2 | m1) != 0) {  // uniform
         const double i2 = ixs[n] * ixs[n];
 #pragma unroll
-        for (int s = 0; s < NSRC; ++s)
-          if ((a.emask >> s) & 1u) sv[s] *= i2;
+        for (int s = 0; s < NSRC; ++s) {
+          if ((m2 >> s) & 1u) sv[s] *= i2;
+          else if ((m1 >> s) & 1u) sv[s] *= ixs[n];
+        }
       }
       if (rs[n] >= top)  // this lane is live through the block (R is a block top)
         sweep_slot<NSRC, B>(acc, Jn[j], Jc[j], ixs[n], sv, top);
     }
-    if (bi == 0) {  // row l = lmin: the x -> 0 E-mode terms (zero unless emask and lmin = 2)
+    if (SC && bi == 0) {  // the x -> 0 limit terms (zero unless a scaled column reaches l = 1 or 2)
+      if (lmin == 1) {
 #pragma unroll
-      for (int s = 0; s < NSRC; ++s) acc[s] += e2[s];
+        for (int s = 0; s < NSRC; ++s) {
+          const bool r1 = (m1 >> s) & 1u;
+          acc[s] += r1 ? elim[s] : 0.0;         // row 1
+          acc[NSRC + s] += r1 ? 0.0 : elim[s];  // row 2
+        }
+      } else if (lmin == 2) {
+#pragma unroll
+        for (int s = 0; s < NSRC; ++s) acc[s] += elim[s];
+      }
     }
     // Each wave leaves its block total in slot bi % nring; every nring/2
     // blocks (bi % (nring/2) == 0) the workgroup synchronises once and wave 0
@@ -315,7 +344,7 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
           double tot = 0.0;
           for (int ww = 0; ww < W; ++ww) tot += cross[((bb & (nring - 1)) * W + ww) * NV + lane];
           const int l = lmin + bb * B + lane / NSRC;
-          if ((a.emask >> (lane % NSRC)) & 1u)
+          if (SC && ((a.emask >> (lane % NSRC)) & 1u))
             tot *= sqrt((double)(l - 1) * (double)l * (double)(l + 1) * (double)(l + 2));
           const int64_t o = out_at(lmin + bb * B);
           if (o >= 0) drow[o] = tot;
@@ -325,9 +354,9 @@ __global__ void __launch_bounds__(512) project_fp64_desc_kernel(ProjectArgs a) {
   }
 }
 
-template <int NSRC, int T, int B, bool SMP>
+template <int NSRC, int T, int B, bool SMP, bool SC>
 hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
-  auto kern = project_fp64_desc_kernel<NSRC, T, B, SMP>;
+  auto kern = project_fp64_desc_kernel<NSRC, T, B, SMP, SC>;
   if (sh.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
@@ -339,24 +368,30 @@ hipError_t launch_t(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s)
   return hipGetLastError();
 }
 
-template <int NSRC, int B, bool SMP>
+template <int NSRC, int B, bool SMP, bool SC>
 hipError_t launch_b(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
   switch (sh.slots) {
-    case 4: return launch_t<NSRC, 4, B, SMP>(a, sh, s);
-    case 8: return launch_t<NSRC, 8, B, SMP>(a, sh, s);
-    case 12: return launch_t<NSRC, 12, B, SMP>(a, sh, s);
-    case 16: return launch_t<NSRC, 16, B, SMP>(a, sh, s);
+    case 4: return launch_t<NSRC, 4, B, SMP, SC>(a, sh, s);
+    case 8: return launch_t<NSRC, 8, B, SMP, SC>(a, sh, s);
+    case 12: return launch_t<NSRC, 12, B, SMP, SC>(a, sh, s);
+    case 16: return launch_t<NSRC, 16, B, SMP, SC>(a, sh, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int NSRC>
 hipError_t launch_n(const ProjectArgs &a, const ProjectShape &sh, hipStream_t s) {
+  // scaled columns or remapped source planes take the SC variant (16-row blocks only)
+  bool sc = (a.emask | a.x1mask | a.x2mask) != 0u;
+  for (int q = 0; q < NSRC; ++q) sc = sc || a.splane[q] != q;
+  if (sc && sh.block != 16) return hipErrorInvalidValue;
   if (a.lsel) {  // multipole sampling: 16-row blocks only
     if (sh.block != 16 || !a.bmask) return hipErrorInvalidValue;
-    return launch_b<NSRC, 16, true>(a, sh, s);
+    return sc ? launch_b<NSRC, 16, true, true>(a, sh, s) : launch_b<NSRC, 16, true, false>(a, sh, s);
   }
-  return sh.block == 16 ? launch_b<NSRC, 16, false>(a, sh, s) : launch_b<NSRC, 8, false>(a, sh, s);
+  if (sc) return launch_b<NSRC, 16, false, true>(a, sh, s);
+  return sh.block == 16 ? launch_b<NSRC, 16, false, false>(a, sh, s)
+                        : launch_b<NSRC, 8, false, false>(a, sh, s);
 }
 
 }  // namespace

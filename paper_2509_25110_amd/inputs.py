@@ -139,6 +139,8 @@ DESCRIPTIONS = {
     "C3": "TT/EE/TE/PP, l=2..5000, 8000 log-k on [1e-4,1.0], 4000 tau on [0,14000]",
     "C4": "256 drawn models, TT/EE/TE/PP, l_max in [1500,5000], 2000..8000 of the 8000 master "
           "log-k on [1e-4,1.0], 3000 tau on [0,14000]",
+    "T2": "tensor modes TT/EE/BB/TE, l=2..1500, 2000 log-k on [1e-4,3000/14000], "
+          "3000 tau on [0,14000]",
 }
 
 
@@ -183,6 +185,45 @@ def l_samples(lmin: int, lmax: int, boost: float = 1.0) -> np.ndarray:
 def small(lmax=40, nk=24, kmax=0.02, ntau=200, nsrc=3, kmin=1e-4, **kw) -> Workload:
     """A small workload of the same structure (for quick parity tests)."""
     return _make("small", lmax=lmax, nk=nk, kmax=kmax, ntau=ntau, nsrc=nsrc, kmin=kmin, **kw)
+
+
+# --- tensor modes ---------------------------------------------------------------------------
+#
+# The tensor line-of-sight call projects a temperature source S_T and a
+# polarisation source S_P (both from gravitational waves) on the tensor
+# kernels; its spectra are TT, EE, BB and TE.  The paper's runs use
+# l_max_tensor = 1500 and k eta_max = 3000 for tensors (Sec. 3.1), i.e. k up to
+# 3000 / tau0.  Synthetic sources of the same structure: S_T an ISW-like term
+# of a wave that decays after horizon entry (k tau > 1) plus a small
+# recombination term, S_P a visibility peak times a wave amplitude that falls
+# off for modes inside the horizon at recombination.
+PAIRS_TENSOR = ((0, 0), (1, 1), (2, 2), (0, 1))  # TT, EE, BB, TE over (T, E, B)
+PAIR_NAMES_TENSOR = ("TT", "EE", "BB", "TE")
+TENSOR_R = 0.1
+
+
+def tensor_sources(k: np.ndarray, tau: np.ndarray, tau_star=280.0, width=20.0) -> np.ndarray:
+    """Synthetic tensor sources S[2, k, tau]: S_T, then S_P."""
+    kk = k[:, None]
+    kt = kk * tau[None, :]
+    g = gauss(tau, tau_star, width)[None, :]
+    S = np.empty((2, k.size, tau.size), dtype=np.float64)
+    S[0] = kk * np.sin(kt) / (1.0 + kt * kt) + 0.05 * g * np.cos(150.0 * kk)
+    S[1] = 0.5 * g * (1.0 + 0.3 * np.cos(150.0 * kk)) / (1.0 + (kk * tau_star) ** 2)
+    return S
+
+
+def tensor_workload(lmax=1500, nk=2000, kmax=3000.0 / TAU0, ntau=3000, kmin=1e-4,
+                    A_s=2.1e-9, r=TENSOR_R, name="T2") -> Workload:
+    """Tensor projection workload: l = 2..lmax, nk log-k on [kmin, kmax], ntau tau nodes;
+    P_t(k) = r A_s (k / 0.05)^(-r/8) (the consistency-relation tilt)."""
+    k = log_k_grid(nk, kmin, kmax)
+    tau = tau_grid(ntau)
+    return Workload(name=name, lmin=2, lmax=lmax, k=k, tau=tau, tau0=TAU0,
+                    w_tau=trapezoid_weights(tau), w_lnk=trapezoid_weights(np.log(k)),
+                    Pk=primordial(k, r * A_s, 1.0 - r / 8.0), S=tensor_sources(k, tau),
+                    pairs=PAIRS_TENSOR, pair_names=PAIR_NAMES_TENSOR,
+                    params=dict(A_s=A_s, r=r))
 
 
 # --- batched configuration: per-model parameter draws -------------------------------------

@@ -33,7 +33,8 @@ _STATUS = {1: "LOS_ERR_INVALID", 2: "LOS_ERR_HIP", 3: "LOS_ERR_OOM", 4: "LOS_ERR
 
 # every symbol include/los.h declares
 EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
-           "los_bessel_table", "los_project", "los_project_kernels", "cl_integrate",
+           "los_bessel_table", "los_project", "los_project_kernels", "los_project_tensor",
+           "cl_integrate",
            "los_spline_sources", "los_interp_sources", "los_project_lsample", "los_cl_interp",
            "los_batch_create",
            "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_solve_timed",
@@ -70,6 +71,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.los_project_kernels.restype = ctypes.c_int
     lib.los_project_kernels.argtypes = [vp, i32, i32, i64, i64, dbl, vp, vp, vp, vp, i32,
                                         ctypes.c_uint32, i32, vp, vp]
+    lib.los_project_tensor.restype = ctypes.c_int
+    lib.los_project_tensor.argtypes = [vp, i32, i32, i64, i64, dbl, vp, vp, vp, vp, vp, vp]
     lib.cl_integrate.restype = ctypes.c_int
     lib.cl_integrate.argtypes = [vp, vp, i32, i32, i32, i64, vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
@@ -228,6 +231,27 @@ class Context:
         _check(lib().los_project_kernels(self._h, lmin, lmax, nk, ntau, float(tau0), _ptr(k),
                                          _ptr(tau), _ptr(w_tau), _ptr(S), nsrc, int(kernel_mask),
                                          prec, _ptr(delta), _stream(stream)))
+        return delta
+
+    def los_project_tensor(self, lmin: int, lmax: int, k: torch.Tensor, tau: torch.Tensor,
+                           tau0: float, w_tau: torch.Tensor, S: torch.Tensor,
+                           delta: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Tensor-mode projection: S is [2, nk, ntau] (S_T, S_P) float64; returns delta
+        [nk, nl, 3] float64 (T, E, B)."""
+        two, nk, ntau = S.shape
+        if two != 2:
+            raise ValueError("S must be [2, nk, ntau] (S_T, S_P)")
+        nl = lmax - lmin + 1
+        if delta is None:
+            delta = torch.empty((nk, nl, 3), dtype=torch.float64, device=S.device)
+        _need(S, torch.float64, 2 * nk * ntau, "S")
+        _need(k, torch.float64, nk, "k")
+        _need(tau, torch.float64, ntau, "tau")
+        _need(w_tau, torch.float64, ntau, "w_tau")
+        _need(delta, torch.float64, nk * nl * 3, "delta")
+        _check(lib().los_project_tensor(self._h, lmin, lmax, nk, ntau, float(tau0), _ptr(k),
+                                        _ptr(tau), _ptr(w_tau), _ptr(S), _ptr(delta),
+                                        _stream(stream)))
         return delta
 
     def cl_integrate(self, delta: torch.Tensor, w_lnk: torch.Tensor, Pk: torch.Tensor,

@@ -9,9 +9,12 @@ multipole:
   without replacement; each model solved alone on its own subset of the
   8000-point master k grid (3000 tau), one line per l of the model:
   ``model l TT EE TE PP``.
+* T2 (tensor modes, l = 2..1500, 2000 log-k on [1e-4, 3000/14000], 3000 tau)
+  -> ``t2_cl_oracle.txt``: the oracle's tensor projection (K^T, K^E, K^B) and
+  its C_l, one line per l: ``l TT EE BB TE``.
 
 Calls only the CPU oracle (and the seeded input generator).
-Run from the repository root: ``python tests/golden/make_golden.py [C2|C3|C4]``.
+Run from the repository root: ``python tests/golden/make_golden.py [C2|C3|C4|T2]``.
 """
 import os
 import sys
@@ -60,9 +63,27 @@ def main_c4():
     print("wrote", out, len(lines), "rows")
 
 
+def main_t2():
+    out = os.path.join(HERE, "t2_cl_oracle.txt")
+    w = inputs.tensor_workload()
+    t = time.time()
+    d = oracle.project_tensor(w.lmin, w.lmax, w.k, w.tau, w.tau0, w.w_tau, w.S)
+    c = oracle.cl(d, w.w_lnk, w.Pk, w.pairs)
+    with open(out, "w") as f:
+        f.write("# oracle tensor-mode C_l, workload T2 (%s), every l; columns: l %s\n"
+                % (inputs.DESCRIPTIONS["T2"], " ".join(w.pair_names)))
+        f.write("# written by tests/golden/make_golden.py with %d oracle threads in %.0f s\n"
+                % (oracle.num_threads(), time.time() - t))
+        for l in range(w.lmin, w.lmax + 1):
+            f.write("%d %s\n" % (l, " ".join(repr(float(v)) for v in c[:, l - w.lmin])))
+    print("wrote", out, w.lmax - w.lmin + 1, "rows")
+
+
 def main(name="C2"):
     if name == "C4":
         return main_c4()
+    if name == "T2":
+        return main_t2()
     out = os.path.join(HERE, "%s_cl_oracle.txt" % name.lower())
     w = inputs.config(name)
     t = time.time()

@@ -96,6 +96,19 @@ def test_project_kernels_validation(lib):
     assert lib.los_project_kernels(ctx, 2, 10, 4, 8, 1.0, p, p, p, p, 2, 0b10, 2, p, None) == 4
 
 
+def test_project_tensor_validation(lib):
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)
+    assert lib.los_project_tensor(None, 2, 10, 4, 8, 1.0, p, p, p, p, p, None) == 1
+    for lmin, lmax, nk, ntau in [(1, 10, 4, 8), (10, 9, 4, 8), (2, 20000, 4, 8), (2, 10, 0, 8),
+                                 (2, 10, 4, 0), (2, 10, 4, 9000)]:
+        rc = lib.los_project_tensor(ctx, lmin, lmax, nk, ntau, 1.0, p, p, p, p, p, None)
+        assert rc == 1, (lmin, lmax, nk, ntau, lib.los_last_error())
+    assert lib.los_project_tensor(ctx, 2, 10, 4, 8, 1.0, p, p, p, None, p, None) == 1
+    assert b"NULL" in lib.los_last_error()
+    assert lib.los_project_tensor(ctx, 2, 10, 4, 8, float("nan"), p, p, p, p, p, None) == 1
+
+
 def test_cl_and_table_validation(lib):
     ctx, _keep = _dummy_ctx()
     p = ctypes.c_void_p(16)
