@@ -17,7 +17,7 @@
 // Workspace slots of a context: the C_l partial sums and the Bessel tables
 // of the MFMA projection live in separate buffers, so a C_l call queued
 // behind a projection never reallocates memory the projection still reads.
-enum { WS_CL = 0, WS_JTAB = 1, WS_SPLINE = 2, WS_LSEL = 3, WS_CLI = 4, WS_COUNT = 5 };
+enum { WS_CL = 0, WS_JTAB = 1, WS_SPLINE = 2, WS_LSEL = 3, WS_CLI = 4, WS_TENSOR = 5, WS_COUNT = 6 };
 
 struct los_ctx {
   int device = 0;
@@ -312,7 +312,8 @@ int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, in
     return fail(LOS_ERR_UNSUPPORTED, "los_project: the E-mode kernel needs the sweep scheme");
   los::ProjectShape sh =
       desc ? los::project_fp64_desc_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"),
-                                          env_int("LOS_PROJ_SLOTS"), env_int("LOS_PROJ_BLOCK"),
+                                          env_int("LOS_PROJ_SLOTS"),
+                                          kernel_mask ? 16 : env_int("LOS_PROJ_BLOCK"),
                                           (size_t)std::max(0, env_int("LOS_PROJ_LDS_EXTRA")))
            : los::project_fp64_shape(nsrc, ntau, env_int("LOS_PROJ_WAVES"),
                                      env_int("LOS_PROJ_SLOTS"));
@@ -346,6 +347,63 @@ int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t nt
                 int32_t nsrc, int32_t prec, void *delta, void *stream) {
   return los_project_kernels(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, S, nsrc, 0u, prec,
                              delta, stream);
+}
+
+int los_project_tensor(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
+                       double tau0, const double *k, const double *tau, const double *w_tau,
+                       const double *S, double *delta, void *stream) {
+  if (!ctx) return fail(LOS_ERR_INVALID, "los_project_tensor: ctx is NULL");
+  if (lmin < 2 || lmax < lmin || lmax > 16000)
+    return fail(LOS_ERR_INVALID, "los_project_tensor: need 2 <= lmin <= lmax <= 16000 (got %d, %d)",
+                lmin, lmax);
+  if (nk < 1 || nk > ((int64_t)1 << 31) - 1)
+    return fail(LOS_ERR_INVALID, "los_project_tensor: nk = %lld out of range", (long long)nk);
+  if (ntau < 1 || ntau > 8192)
+    return fail(LOS_ERR_INVALID, "los_project_tensor: ntau = %lld out of [1, 8192]",
+                (long long)ntau);
+  if (!(tau0 == tau0)) return fail(LOS_ERR_INVALID, "los_project_tensor: tau0 is NaN");
+  if (!k || !tau || !w_tau || !S || !delta)
+    return fail(LOS_ERR_INVALID, "los_project_tensor: NULL array");
+  const char *scheme = std::getenv("LOS_PROJ_SCHEME");
+  if (scheme && std::atoi(scheme) == 0)
+    return fail(LOS_ERR_UNSUPPORTED, "los_project_tensor: needs the sweep scheme");
+  // the sweep: rows lmin-1 .. lmax, columns S_P, S_P/x, S_P/x^2, S_T/x^2
+  los::ProjectShape sh = los::project_fp64_desc_shape(
+      4, ntau, env_int("LOS_PROJ_WAVES"), env_int("LOS_PROJ_SLOTS"), 16,
+      (size_t)std::max(0, env_int("LOS_PROJ_LDS_EXTRA")));
+  if (sh.waves == 0 || sh.lds > 160 * 1024)
+    return fail(LOS_ERR_UNSUPPORTED, "los_project_tensor: no launch shape for ntau = %lld",
+                (long long)ntau);
+  const int nl = lmax - lmin + 1;
+  void *ws = nullptr;
+  int rc = ws_reserve(ctx, WS_TENSOR, sizeof(double) * 4 * (size_t)(nl + 1) * (size_t)nk, &ws);
+  if (rc != LOS_OK) return rc;
+  los::ProjectArgs a{};
+  a.lmin = lmin - 1;
+  a.lmax = lmax;
+  a.nl = nl + 1;
+  a.nblk = (a.nl + los::kProjectBlock - 1) / los::kProjectBlock;
+  a.nk = nk;
+  a.ntau = ntau;
+  a.tau0 = tau0;
+  a.k = k;
+  a.tau = tau;
+  a.w = w_tau;
+  a.S = S;
+  a.delta = (double *)ws;
+  a.emask = 0u;
+  a.x1mask = 0x2u;  // column 1: S_P / x
+  a.x2mask = 0xcu;  // columns 2, 3: S_P / x^2, S_T / x^2
+  a.splane[0] = 1;
+  a.splane[1] = 1;
+  a.splane[2] = 1;
+  a.splane[3] = 0;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = los::project_fp64_desc_launch(a, 4, sh, st);
+  if (e != hipSuccess) return hip_fail(e, "los_project_tensor: sweep launch");
+  e = los::tensor_combine_launch((const double *)ws, delta, lmin, nl, nk, st);
+  if (e != hipSuccess) return hip_fail(e, "los_project_tensor: combine launch");
+  return ok();
 }
 
 int los_project_lsample(los_ctx *ctx, int32_t lmin, int32_t lmax, const int32_t *ls,
