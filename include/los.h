@@ -199,6 +199,29 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
                  int32_t npairs, double *cl, void *stream);
 
 /*
+ * cl_integrate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and result as cl_integrate (bitwise), but the
+ * partial sums live in a fixed device array of the library (16 MiB per GPU,
+ * held until the process ends) instead of the context workspace, and the call
+ * makes no allocation of any kind.  The array's device address is looked up
+ * once per device by los_ctx_create, so the context must have been created on
+ * the current device.
+ * Limit: the partial sums take 8 * nseg * npairs * nl bytes, nseg =
+ * min(nk, 1024, ceil(4096 / ceil(nl / 64))) (about 2.2 MB per pair, e.g.
+ * 8.9 MB for 4 pairs at nl = 16000); a larger request fails with
+ * LOS_ERR_INVALID and a message naming the size (use cl_integrate).
+ * Every call on a GPU shares that GPU's array, and nothing in it needs to be
+ * cleared between calls: calls that overlap on one GPU (several streams or
+ * host threads at once) race and give wrong results.
+ * Errors: as cl_integrate, plus LOS_ERR_INVALID when the current device is
+ * not the context's.
+ */
+int cl_integrate_noalloc(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc,
+                         int32_t nl, int64_t nk, const double *w_lnk, const double *Pk,
+                         const int32_t *pairs, int32_t npairs, double *cl, void *stream);
+
+/*
  * Multipole sampling (Sec. 3.1: the output l-sampling density sets how many
  * multipoles are computed explicitly; the others are interpolated).
  *

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,7 @@ enum { WS_CL = 0, WS_JTAB = 1, WS_SPLINE = 2, WS_LSEL = 3, WS_CLI = 4, WS_TENSOR
 
 struct los_ctx {
   int device = 0;
+  void *scratch = nullptr;  // device address of `scratch` on this device (cl_integrate_noalloc)
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};
   // multipole list whose sample tables are in WS_LSEL ({lmin, lmax, ls...})
@@ -32,6 +34,14 @@ struct los_ctx {
 namespace {
 thread_local std::string g_err;
 }  // namespace
+
+// Device memory of the entry point that allocates nothing (cl_integrate_noalloc):
+// room for the partial sums of the C_l reduction.  Each GPU the library runs on
+// holds its own copy until the process ends; every call on a GPU shares it.
+// In host code `scratch` is only a stand-in for the symbol: its device address
+// (per device) comes from hipGetSymbolAddress in scratch_setup.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 namespace los {
 
@@ -85,6 +95,28 @@ int ws_reserve(los_ctx *ctx, int slot, size_t bytes, void **out) {
   }
   ctx->ws_bytes[slot] = want;
   *out = ctx->ws[slot];
+  return LOS_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev, which must be current; looked
+// up once per device and kept.
+int scratch_setup(int dev, void **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(LOS_ERR_UNSUPPORTED, "device index %d is beyond %d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(LOS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return LOS_OK;
 }
 
@@ -242,9 +274,13 @@ int los_ctx_create(los_ctx **ctx) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  void *sp = nullptr;
+  int rc = scratch_setup(dev, &sp);
+  if (rc != LOS_OK) return rc;
   los_ctx *c = new (std::nothrow) los_ctx;
   if (!c) return fail(LOS_ERR_OOM, "los_ctx_create: out of host memory");
   c->device = dev;
+  c->scratch = sp;
   *ctx = c;
   return ok();
 }
@@ -497,44 +533,90 @@ int los_project_lsample(los_ctx *ctx, int32_t lmin, int32_t lmax, const int32_t 
   return ok();
 }
 
-int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc, int32_t nl,
-                 int64_t nk, const double *w_lnk, const double *Pk, const int32_t *pairs,
-                 int32_t npairs, double *cl, void *stream) {
-  if (!ctx) return fail(LOS_ERR_INVALID, "cl_integrate: ctx is NULL");
-  if (nsrc < 1 || nsrc > 4) return fail(LOS_ERR_INVALID, "cl_integrate: nsrc = %d", nsrc);
-  if (nl < 1) return fail(LOS_ERR_INVALID, "cl_integrate: nl = %d", nl);
-  if (nk < 1) return fail(LOS_ERR_INVALID, "cl_integrate: nk = %lld", (long long)nk);
+}  // extern "C"
+
+namespace {
+
+// Validation shared by cl_integrate and cl_integrate_noalloc; fills everything
+// of `a` except the partial-sum buffer.
+int cl_args(const char *who, los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc,
+            int32_t nl, int64_t nk, const double *w_lnk, const double *Pk, const int32_t *pairs,
+            int32_t npairs, double *cl, los::ClArgs *a) {
+  if (!ctx) return fail(LOS_ERR_INVALID, "%s: ctx is NULL", who);
+  if (nsrc < 1 || nsrc > 4) return fail(LOS_ERR_INVALID, "%s: nsrc = %d", who, nsrc);
+  if (nl < 1) return fail(LOS_ERR_INVALID, "%s: nl = %d", who, nl);
+  if (nk < 1) return fail(LOS_ERR_INVALID, "%s: nk = %lld", who, (long long)nk);
   if (npairs < 1 || npairs > 16)
-    return fail(LOS_ERR_INVALID, "cl_integrate: npairs = %d out of [1, 16]", npairs);
+    return fail(LOS_ERR_INVALID, "%s: npairs = %d out of [1, 16]", who, npairs);
   if (!delta || !w_lnk || !Pk || !pairs || !cl)
-    return fail(LOS_ERR_INVALID, "cl_integrate: NULL array");
+    return fail(LOS_ERR_INVALID, "%s: NULL array", who);
   if (delta_prec != LOS_FP64 && delta_prec != LOS_FP32)
-    return fail(LOS_ERR_INVALID, "cl_integrate: delta_prec must be LOS_FP64 or LOS_FP32");
-  los::ClArgs a{};
+    return fail(LOS_ERR_INVALID, "%s: delta_prec must be LOS_FP64 or LOS_FP32", who);
+  *a = los::ClArgs{};
   for (int p = 0; p < npairs; ++p) {
     if (pairs[2 * p] < 0 || pairs[2 * p] >= nsrc || pairs[2 * p + 1] < 0 ||
         pairs[2 * p + 1] >= nsrc)
-      return fail(LOS_ERR_INVALID, "cl_integrate: pair %d = (%d, %d) out of [0, %d)", p,
+      return fail(LOS_ERR_INVALID, "%s: pair %d = (%d, %d) out of [0, %d)", who, p,
                   pairs[2 * p], pairs[2 * p + 1], nsrc);
-    a.pa[p] = pairs[2 * p];
-    a.pb[p] = pairs[2 * p + 1];
+    a->pa[p] = pairs[2 * p];
+    a->pb[p] = pairs[2 * p + 1];
   }
-  a.delta = delta;
-  a.delta_f32 = delta_prec == LOS_FP32;
-  a.nsrc = nsrc;
-  a.nl = nl;
-  a.npairs = npairs;
-  a.nk = nk;
-  a.w = w_lnk;
-  a.P = Pk;
-  a.cl = cl;
-  a.nseg = los::cl_segments(nk, nl);
+  a->delta = delta;
+  a->delta_f32 = delta_prec == LOS_FP32;
+  a->nsrc = nsrc;
+  a->nl = nl;
+  a->npairs = npairs;
+  a->nk = nk;
+  a->w = w_lnk;
+  a->P = Pk;
+  a->cl = cl;
+  a->nseg = los::cl_segments(nk, nl);
+  return LOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc, int32_t nl,
+                 int64_t nk, const double *w_lnk, const double *Pk, const int32_t *pairs,
+                 int32_t npairs, double *cl, void *stream) {
+  los::ClArgs a;
+  int rc = cl_args("cl_integrate", ctx, delta, delta_prec, nsrc, nl, nk, w_lnk, Pk, pairs, npairs,
+                   cl, &a);
+  if (rc != LOS_OK) return rc;
   void *ws = nullptr;
-  int rc = ws_reserve(ctx, WS_CL, sizeof(double) * (size_t)a.nseg * npairs * nl, &ws);
+  rc = ws_reserve(ctx, WS_CL, sizeof(double) * (size_t)a.nseg * npairs * nl, &ws);
   if (rc != LOS_OK) return rc;
   a.partial = (double *)ws;
   hipError_t e = los::cl_launch(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "cl_integrate launch");
+  return ok();
+}
+
+int cl_integrate_noalloc(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc,
+                         int32_t nl, int64_t nk, const double *w_lnk, const double *Pk,
+                         const int32_t *pairs, int32_t npairs, double *cl, void *stream) {
+  los::ClArgs a;
+  int rc = cl_args("cl_integrate_noalloc", ctx, delta, delta_prec, nsrc, nl, nk, w_lnk, Pk, pairs,
+                   npairs, cl, &a);
+  if (rc != LOS_OK) return rc;
+  const size_t need = sizeof(double) * (size_t)a.nseg * npairs * nl;
+  if (need > kScratchBytes)
+    return fail(LOS_ERR_INVALID,
+                "cl_integrate_noalloc: needs %zu bytes of scratch (%d segments x %d pairs x %d "
+                "multipoles, FP64), more than its fixed %zu; use cl_integrate",
+                need, a.nseg, npairs, nl, kScratchBytes);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "cl_integrate_noalloc: hipGetDevice");
+  if (dev != ctx->device || !ctx->scratch)
+    return fail(LOS_ERR_INVALID,
+                "cl_integrate_noalloc: the current device (%d) is not the context's (%d)", dev,
+                ctx->device);
+  a.partial = (double *)ctx->scratch;
+  e = los::cl_launch(a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "cl_integrate_noalloc launch");
   return ok();
 }
 

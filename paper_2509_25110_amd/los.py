@@ -34,7 +34,7 @@ _STATUS = {1: "LOS_ERR_INVALID", 2: "LOS_ERR_HIP", 3: "LOS_ERR_OOM", 4: "LOS_ERR
 # every symbol include/los.h declares
 EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
            "los_bessel_table", "los_project", "los_project_kernels", "los_project_tensor",
-           "cl_integrate",
+           "cl_integrate", "cl_integrate_noalloc",
            "los_spline_sources", "los_interp_sources", "los_project_lsample", "los_cl_interp",
            "los_batch_create",
            "los_batch_columns", "los_batch_info", "los_batch_solve", "los_batch_solve_timed",
@@ -76,6 +76,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cl_integrate.restype = ctypes.c_int
     lib.cl_integrate.argtypes = [vp, vp, i32, i32, i32, i64, vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
+    lib.cl_integrate_noalloc.restype = ctypes.c_int
+    lib.cl_integrate_noalloc.argtypes = [vp, vp, i32, i32, i32, i64, vp, vp,
+                                         ctypes.POINTER(ctypes.c_int32), i32, vp, vp]
     lib.los_project_lsample.restype = ctypes.c_int
     lib.los_project_lsample.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int32), i32, i64,
                                         i64, dbl, vp, vp, vp, vp, i32, ctypes.c_uint32, vp, vp]
@@ -271,6 +274,23 @@ class Context:
                                   arr, npairs, _ptr(cl), _stream(stream)))
         return cl
 
+
+    def cl_integrate_noalloc(self, delta: torch.Tensor, w_lnk: torch.Tensor, Pk: torch.Tensor,
+                             pairs: Sequence[Tuple[int, int]], cl: torch.Tensor,
+                             stream=None) -> torch.Tensor:
+        """cl_integrate into a caller-supplied `cl`, with the library's fixed device scratch
+        (no allocation by the library)."""
+        nk, nl, nsrc = delta.shape
+        prec = LOS_FP64 if delta.dtype == torch.float64 else LOS_FP32
+        flat = [int(v) for p in pairs for v in p]
+        npairs = len(flat) // 2
+        arr = (ctypes.c_int32 * len(flat))(*flat)
+        _need(w_lnk, torch.float64, nk, "w_lnk")
+        _need(Pk, torch.float64, nk, "Pk")
+        _need(cl, torch.float64, npairs * nl, "cl")
+        _check(lib().cl_integrate_noalloc(self._h, _ptr(delta), prec, nsrc, nl, nk, _ptr(w_lnk),
+                                          _ptr(Pk), arr, npairs, _ptr(cl), _stream(stream)))
+        return cl
 
     def los_project_lsample(self, lmin: int, lmax: int, ls, k: torch.Tensor, tau: torch.Tensor,
                             tau0: float, w_tau: torch.Tensor, S: torch.Tensor, kernel_mask: int = 0,

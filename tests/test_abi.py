@@ -109,6 +109,20 @@ def test_project_tensor_validation(lib):
     assert lib.los_project_tensor(ctx, 2, 10, 4, 8, float("nan"), p, p, p, p, p, None) == 1
 
 
+def test_cl_noalloc_validation(lib):
+    ctx, _keep = _dummy_ctx()
+    p = ctypes.c_void_p(16)
+    pairs = (ctypes.c_int32 * 2)(0, 0)
+    assert lib.cl_integrate_noalloc(None, p, 0, 1, 10, 4, p, p, pairs, 1, p, None) == 1
+    assert b"ctx" in lib.los_last_error()
+    assert lib.cl_integrate_noalloc(ctx, p, 0, 0, 10, 4, p, p, pairs, 1, p, None) == 1  # nsrc = 0
+    assert lib.cl_integrate_noalloc(ctx, None, 0, 1, 10, 4, p, p, pairs, 1, p, None) == 1
+    # 16 pairs at 16000 multipoles need more partial sums than the fixed scratch holds
+    many = (ctypes.c_int32 * 32)(*([0, 0] * 16))
+    assert lib.cl_integrate_noalloc(ctx, p, 0, 1, 16000, 20, p, p, many, 16, p, None) == 1
+    assert b"scratch" in lib.los_last_error()
+
+
 def test_cl_and_table_validation(lib):
     ctx, _keep = _dummy_ctx()
     p = ctypes.c_void_p(16)
