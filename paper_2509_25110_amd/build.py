@@ -21,8 +21,17 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblos.so")
 
-SOURCES = ["los_api.cpp", "bessel_table.hip", "project_fp64.hip", "project_fp64_desc.hip", "cl_reduce.hip", "jtable.hip",
-           "project_mfma.hip", "project_mfma_lds.hip", "project_fused.hip", "batch_cl.hip", "batch_api.cpp", "spline.hip", "cl_interp.hip", "tensor.hip", "emu_kernels.hip", "emu_api.cpp"]
+# heaviest translation units first (the pool compiles them in this order)
+SOURCES = ["project_fp64_desc_n3.hip", "project_fp64_desc_n4.hip", "project_fp64_desc_n3s.hip",
+           "project_fp64_desc_n4s.hip", "project_fp64_desc_n2.hip", "project_fp64_desc_n2s.hip",
+           "project_fp64_desc_n1.hip", "project_fp64_desc_n1s.hip", "project_fp64.hip",
+           "emu_kernels.hip", "project_fused.hip", "project_mfma.hip", "project_mfma_lds.hip",
+           "spline.hip", "los_api.cpp", "batch_api.cpp", "emu_api.cpp", "bessel_table.hip",
+           "project_fp64_desc.hip", "cl_reduce.hip", "jtable.hip", "batch_cl.hip", "cl_interp.hip",
+           "tensor.hip"]
+# host build of the Bessel seed functions, for CPU checks (not linked into liblos.so)
+HOSTCHECK_SRC = "bessel_host_check.cpp"
+HOSTCHECK_LIB = os.path.join(PKG, "liblos_hostcheck.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -78,7 +87,21 @@ def build(verbose: bool = True, incremental: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
+    build_hostcheck(verbose)
     return LIB
+
+
+def build_hostcheck(verbose: bool = True) -> str:
+    """Host-only shared library of the seed functions in bessel_dev.hpp (CPU tests)."""
+    tmp = HOSTCHECK_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *CFLAGS, "-shared", "-x", "hip", os.path.join(CSRC, HOSTCHECK_SRC), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (HOSTCHECK_SRC, " ".join(cmd), r.stderr))
+    os.replace(tmp, HOSTCHECK_LIB)
+    if verbose:
+        print("built", HOSTCHECK_LIB)
+    return HOSTCHECK_LIB
 
 
 if __name__ == "__main__":
