@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct los_ctx;
+
 namespace los {
 
 // l rows per block of the projection kernels (also the granularity of the
@@ -118,7 +120,8 @@ hipError_t mfma_gemm_launch(const GemmArgs &a, int prec, const GemmTile &t, int 
 // (project_fused.hip).  Rows of a chunk as for GemmArgs (k0, row_index for
 // the k value, col_cnt / col_off / s_* / dtrans / delta for S and the
 // output).  Workspace per chunk row: seeds at every 32-row segment top,
-// 1/x and the top row R of every node (fused_workspace_at).
+// 1/x and the top row R of every node, the largest R of every 64 nodes
+// (fused_workspace_at).
 struct FusedArgs {
   int lmin, lmax, nl, nlb, nseg;   // nseg = segments of 32 rows covering 16 * nlb rows
   int64_t ntau, ntp;               // ntp: nodes padded to a multiple of 64
@@ -129,6 +132,7 @@ struct FusedArgs {
   double2 *seed;                   // [kcount][nseg][ntp]
   double *nix;                     // [kcount][ntp]
   int *rtop;                       // [kcount][ntp]
+  int *cmax;                       // [kcount][ntp / 64] largest R of each chunk of 64 nodes
   const float *S;
   int64_t s_kstride, s_cstride;
   int ncol;
@@ -174,6 +178,9 @@ hipError_t batch_cl_launch(const BatchClArgs &a, hipStream_t s);
 // receives (Delta^T, Delta^E, Delta^B) for l = lmin .. lmax.
 hipError_t tensor_combine_launch(const double *d4, double *out, int lmin, int nl, int64_t nk,
                                  hipStream_t s);
+
+// The batch autotune cache file of a context (los_api.cpp), or nullptr.
+const char *ctx_tune_cache(const los_ctx *ctx);
 
 // Error reporting shared by the C entry points (los_api.cpp).
 int fail(int code, const char *fmt, ...);

@@ -6,10 +6,14 @@
 //   pair w (j_R, j_{R+1}) (node_top_pair), then ONE descending sweep that
 //   leaves, at the top row of every 32-row segment at or below R, the pair
 //   (w j_T, w j_{T+1}), T = min(R, segment top), in a seed table; also 1/x
-//   and R per node.  Nothing of J itself is stored.
+//   and R per node and the largest R of every chunk of 64 nodes.  Nothing of
+//   J itself is stored.
 //
 // fused_gemm_kernel (one workgroup per (k row, TM-row l tile, TN-column
-//   tile)): the tau axis advances in chunks of 64 nodes.  Per chunk every
+//   tile)): the tau axis advances in chunks of 64 nodes, visiting only the
+//   chunks whose largest R reaches the tile (two ballots over the chunk
+//   table), and the sources, seeds and R of the next such chunk are loaded
+//   while the matrix cores work on the current one.  Per chunk every
 //   wave regenerates one 32-row segment of the l tile for the 64 nodes from
 //   the seeds (FP64 recurrence in registers, one lane per node, rounded to
 //   FP32 -- or split into bf16 hi/lo -- as it is written to LDS), the S
@@ -26,7 +30,8 @@
 //   nix[kc * ntp + n]                  1 / x (0 where R < 0)
 //   seed[(kc * nseg + s) * ntp + n]    (w j_T, w j_{T+1}), T = min(R, lmin + 32 s + 31),
 //                                      written for segments with lmin + 32 s <= R
-// ntp = nodes padded to a multiple of 64.
+//   cmax[kc * (ntp / 64) + c]          max of rtop over nodes 64 c .. 64 c + 63
+// ntp = nodes padded to a multiple of 64 (at most 8192, so at most 128 chunks).
 #include "bessel_dev.hpp"
 #include "los_internal.hpp"
 
@@ -43,6 +48,20 @@ __device__ inline int wave_max_int(int v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+// Smallest set bit >= from of the 128-bit mask (a1:a0), or -1.
+__device__ inline int next_chunk(uint64_t a0, uint64_t a1, int from) {
+  if (from < 64) {
+    const uint64_t m = a0 & (~0ull << from);
+    if (m) return __ffsll((unsigned long long)m) - 1;
+    from = 64;
+  }
+  if (from < 128) {
+    const uint64_t m = a1 & (~0ull << (from - 64));
+    if (m) return 64 + __ffsll((unsigned long long)m) - 1;
+  }
+  return -1;
 }
 
 // ------------------------------------------------------------------ seeds
@@ -62,6 +81,10 @@ __global__ __launch_bounds__(256) void jseed_kernel(FusedArgs a) {
       R = node_top_pair(x, ix, wt, a.lmin, a.lmax, cur, nxt);
     }
   }
+  // every lane of the wave is here (ntp is a multiple of 64): the wave's 64
+  // nodes are chunk n / 64
+  const int cm = wave_max_int(R);
+  if ((threadIdx.x & 63) == 0) a.cmax[(int64_t)ki * (a.ntp / KB) + (n / KB)] = cm;
   const int64_t nb = (int64_t)ki * a.ntp + n;
   a.rtop[nb] = R;
   a.nix[nb] = R >= 0 ? ix : 0.0;
@@ -170,16 +193,37 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
 #pragma unroll
     for (int j = 0; j < NBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  const int nch = (int)(a.ntp / KB);
-  for (int c = 0; c < nch; ++c) {
-    const int n = c * KB + lane;
-    const int Rn = a.rtop[rowb + n];
-    const int cmax = wave_max_int(Rn);               // the same in every wave
-    if (cmax < a.lmin + tile_lo) continue;           // chunk holds no row of this tile
-    const int top_tr = min(cmax - a.lmin - tile_lo, top_cap);
+  // Column blocks whose models stop below a row block skip its products: the
+  // last 16-row block (relative to the tile) that column block j of this wave
+  // needs, from the l_max of its first column (columns are ordered by l_max,
+  // largest first, within a row).
+  int jlast[NBW];
+#pragma unroll
+  for (int j = 0; j < NBW; ++j) {
+    const int cj = c0 + wc * NBW * 16 + 16 * j;
+    jlast[j] = (a.col_lmax && cj < ncol) ? ((a.col_lmax[a.col_off[r] + cj] - a.lmin) >> 4) - lb0
+                                         : (cj < ncol ? a.nlb - 1 - lb0 : -1);
+  }
 
-    // S columns of the tile for these 64 nodes (global -> registers)
-    float4 sv[SPT];
+  // Active chunks: those whose largest top row reaches the tile's first row.
+  const int nch = (int)(a.ntp / KB);  // <= 128
+  const int *cmr = a.cmax + (int64_t)ki * nch;
+  const int thr = a.lmin + tile_lo;
+  const int cm0 = lane < nch ? cmr[lane] : -1;
+  const int cm1 = lane + 64 < nch ? cmr[lane + 64] : -1;
+  const uint64_t act0 = __ballot(cm0 >= thr), act1 = __ballot(cm1 >= thr);
+
+  // Per-chunk inputs, loaded one active chunk ahead: R, seed pair and 1/x of
+  // this lane's node, and this thread's pieces of the S tile.
+  int Rn = -1;
+  double2 sd = make_double2(0.0, 0.0);
+  double nx = 0.0;
+  float4 sv[SPT];
+  auto load_chunk = [&](int c) {
+    const int n = c * KB + lane;
+    Rn = a.rtop[rowb + n];
+    nx = a.nix[rowb + n];
+    if (seg_ok) sd = seedp[n];  // read whatever the node's R; used only below R
 #pragma unroll
     for (int p = 0; p < SPT; ++p) {
       if (SP % NT != 0 && p * NT + tid >= SP) break;
@@ -196,19 +240,20 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
         sv[p] = make_float4(t4[0], t4[1], t4[2], t4[3]);
       }
     }
+  };
+
+  int c = next_chunk(act0, act1, 0);
+  if (c >= 0) load_chunk(c);
+  while (c >= 0) {
+    const int cmax = __shfl(c < 64 ? cm0 : cm1, c & 63, 64);  // the chunk's largest R
+    const int top_tr = min(cmax - a.lmin - tile_lo, top_cap);
 
     // regenerate this wave's segment for the 64 nodes (zeros above each node's R)
     if (seg_ok && 32 * w <= top_tr) {
       const int Rrel = Rn - a.lmin;                  // < 0 when the node has no row
       const bool liveA = Rn >= 0 && Rrel >= seg_hi;  // live through the upper 16 rows
       const bool liveB = Rn >= 0 && Rrel >= seg_hi - 16;
-      double cur = 0.0, nxt = 0.0, ix = 0.0;
-      if (liveB) {
-        const double2 sd = seedp[n];
-        cur = sd.x;
-        nxt = sd.y;
-        ix = a.nix[rowb + n];
-      }
+      double cur = liveB ? sd.x : 0.0, nxt = liveB ? sd.y : 0.0, ix = liveB ? nx : 0.0;
       const double d2 = ix + ix;
 #pragma unroll
       for (int half = 1; half >= 0; --half) {
@@ -262,6 +307,9 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
       }
     }
     __syncthreads();
+    // the next active chunk's inputs are in flight while the matrix cores run
+    const int cn = next_chunk(act0, act1, c + 1);
+    if (cn >= 0) load_chunk(cn);
 
     // this wave's rows: blocks wr*MBW .. +MBW-1 of the tile; those <= top_tr hold data
     const int nb = min(MBW, (top_tr - wr * MBW * 16) / 16 + 1);
@@ -286,10 +334,12 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
               const float af[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
 #pragma unroll
               for (int j = 0; j < NBW; ++j)
+                if (wr * MBW + i <= jlast[j]) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e], acc[i][j],
-                                                                   0, 0, 0);
+                  for (int e = 0; e < 8; ++e)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e], acc[i][j],
+                                                                     0, 0, 0);
+                }
             }
           }
         } else {
@@ -307,17 +357,19 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
               const bf8 ah = *(const bf8 *)(Jh + row * LD + kofs);
               const bf8 al = *(const bf8 *)(Jl + row * LD + kofs);
 #pragma unroll
-              for (int j = 0; j < NBW; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-              }
+              for (int j = 0; j < NBW; ++j)
+                if (wr * MBW + i <= jlast[j]) {
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+                }
             }
           }
         }
       }
     }
     __syncthreads();
+    c = cn;
   }
 
   // output: lane holds rows 4g + v of each 16-row block, column r16 of each column block
@@ -390,7 +442,8 @@ FusedShape fused_shape_at(int i) {
 }
 
 size_t fused_seed_bytes_per_row(int nseg, int64_t ntp) {
-  return (size_t)ntp * (sizeof(int) + sizeof(double) + sizeof(double2) * (size_t)nseg);
+  return (size_t)ntp * (sizeof(int) + sizeof(double) + sizeof(double2) * (size_t)nseg) +
+         sizeof(int) * (size_t)(ntp / KB);
 }
 
 void fused_workspace_at(FusedArgs &a, void *ws, int kcount) {
@@ -400,6 +453,8 @@ void fused_workspace_at(FusedArgs &a, void *ws, int kcount) {
   a.nix = (double *)p;
   p += sizeof(double) * (size_t)a.ntp * kcount;
   a.rtop = (int *)p;
+  p += sizeof(int) * (size_t)a.ntp * kcount;
+  a.cmax = (int *)p;
 }
 
 hipError_t jseed_launch(const FusedArgs &a, int kcount, hipStream_t s) {
