@@ -69,9 +69,16 @@ const char *los_last_error(void);
 const char *los_version(void);
 
 /* Create a context bound to the current HIP device.  *ctx receives a handle
- * owned by the caller and released with los_ctx_destroy.  Errors:
- * LOS_ERR_INVALID (ctx == NULL), LOS_ERR_HIP (no device). */
-int los_ctx_create(los_ctx **ctx);
+ * owned by the caller and released with los_ctx_destroy.
+ * tune_cache_path (host string, may be NULL): a text file where batch plans
+ * created with this context look up the tile shape their autotuner chose
+ * before, under a key of the device architecture, the precision, the pipeline
+ * and buckets of n_tau, the multipole count, the widest master row and the row
+ * count, and append a line after they tune; a plan that finds its key skips
+ * the tuning.  The file need not exist; unreadable lines are ignored; lines are
+ * appended with one write each.  NULL: every plan tunes itself.
+ * Errors: LOS_ERR_INVALID (ctx == NULL), LOS_ERR_HIP (no device). */
+int los_ctx_create(los_ctx **ctx, const char *tune_cache_path);
 
 /* Release a context and its device workspace.  Waits for nothing: the caller
  * must make sure no work that uses the context is still queued.  NULL is a
@@ -436,6 +443,35 @@ int emu_train(los_emu *emu, const double *params, const double *lo, const double
               float *loss_hist, void *stream);
 int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *err,
               uint8_t *need_fallback, double threshold, void *stream);
+
+/*
+ * Fallback merge: the rows of an emu_infer result that the caller re-solved
+ * with the plain method (los_batch_solve on those models) replace the
+ * emulator's values, on `stream`:
+ *   cl[rows[i]][p][l] = cl_solved[i][p][l]   (p < 4, l < nl), i < nf,
+ *   err[rows[i]] = 0, need_fallback[rows[i]] = 0   (err, need_fallback may be NULL).
+ * rows: HOST, nf distinct indices in [0, n); cl_solved, cl: device doubles
+ * [nf][4][nl] and [n][4][nl] (same layout as emu_infer's output).  nf == 0 is
+ * a no-op.  Errors: LOS_ERR_INVALID for bad or repeated rows.
+ */
+int emu_merge(los_emu *emu, const int64_t *rows, int64_t nf, const double *cl_solved, double *cl,
+              int64_t n, float *err, uint8_t *need_fallback, void *stream);
+
+/*
+ * Checkpoints.  emu_save waits for `stream` (the stream of the emulator's last
+ * calls), then writes to `path` a versioned file: a header with the shape
+ * (nparam, nl, ncomp, width, depth, members) and seed, every member's
+ * parameters and Adam moments (FP32), and, once trained, lo/hi, the PCA mean,
+ * basis and sigma and the TE scale t_l (FP64), followed by a 64-bit FNV-1a
+ * checksum.  emu_load creates an emulator on ctx's device from such a file;
+ * *emu receives it (owned by the caller, released with emu_destroy); inference
+ * from it is bitwise that of the emulator that was saved.  Errors:
+ * LOS_ERR_INVALID for an unreadable, truncated, corrupt or foreign file,
+ * LOS_ERR_UNSUPPORTED for another version, LOS_ERR_OOM / LOS_ERR_HIP from the
+ * device.
+ */
+int emu_save(const los_emu *emu, const char *path, void *stream);
+int emu_load(los_ctx *ctx, const char *path, los_emu **emu);
 
 #ifdef __cplusplus
 }

@@ -20,9 +20,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "los.h"
@@ -61,6 +63,7 @@ struct los_batch {
   los::GemmTile tile{2, 4};
   bool tuned = false;
   float tune_ms[los::kGemmTileCount] = {};
+  std::string cache_path, cache_key;  // autotune cache (empty: none)
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
   const void *key[9] = {};
@@ -94,6 +97,81 @@ void free_plan(los_batch *b) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
+}
+
+// Autotune cache: one line per tuning, "<key> <value>"; the last line with a
+// plan's key wins.  Key: architecture, pipeline, precision and buckets of the
+// shape (n_tau padded to 64, multipoles in 256s, widest row and row count in
+// powers of two); value: the fused shape index or the table tile "mb x nc".
+int pow2_bucket(int64_t v) {
+  int b = 0;
+  while (v > 1) {
+    v = (v + 1) / 2;
+    ++b;
+  }
+  return b;
+}
+
+std::string tune_key(const los_batch *b, int maxcol) {
+  hipDeviceProp_t prop{};
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s %s prec=%d ntau=%lld nl=%d col=%d rows=%d", arch.c_str(),
+                b->fused ? "fused" : "table", b->prec, (long long)((b->ntau + 63) / 64 * 64),
+                (b->nl + 255) / 256 * 256, pow2_bucket(maxcol), pow2_bucket(b->nrows));
+  return buf;
+}
+
+// The cached value for the plan's key, or "" when there is none.
+std::string cache_lookup(const los_batch *b) {
+  std::string found;
+  FILE *f = std::fopen(b->cache_path.c_str(), "r");
+  if (!f) return found;
+  char line[512];
+  const size_t kl = b->cache_key.size();
+  while (std::fgets(line, sizeof line, f)) {
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    if (l.size() > kl + 1 && l.compare(0, kl, b->cache_key) == 0 && l[kl] == ' ')
+      found = l.substr(kl + 1);
+  }
+  std::fclose(f);
+  return found;
+}
+
+// Apply a cached value; false when it names nothing this build has compiled.
+bool cache_apply(los_batch *b, const std::string &v) {
+  if (b->fused) {
+    int sh = -1;
+    if (std::sscanf(v.c_str(), "shape=%d", &sh) != 1 || sh < 0 || sh >= los::kFusedShapeCount)
+      return false;
+    b->fshape = sh;
+    return true;
+  }
+  los::GemmTile t{0, 0};
+  if (std::sscanf(v.c_str(), "tile=%dx%d", &t.mb, &t.nc) != 2 || !los::gemm_tile_supported(t) ||
+      (t.mb == los::kGemmTileLds.mb && t.nc == los::kGemmTileLds.nc && b->prec != LOS_BF16X3))
+    return false;
+  b->tile = t;
+  return true;
+}
+
+void cache_store(const los_batch *b) {
+  if (b->cache_path.empty()) return;
+  char val[64];
+  if (b->fused)
+    std::snprintf(val, sizeof val, "shape=%d", b->fshape);
+  else
+    std::snprintf(val, sizeof val, "tile=%dx%d", b->tile.mb, b->tile.nc);
+  const std::string line = b->cache_key + " " + val + "\n";
+  FILE *f = std::fopen(b->cache_path.c_str(), "a");
+  if (!f) return;  // a cache that cannot be written only costs the next plan a tuning
+  std::fwrite(line.data(), 1, line.size(), f);
+  std::fclose(f);
 }
 
 struct SolveArgs {
@@ -242,6 +320,10 @@ int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
     b->tuned = true;
     return LOS_OK;
   }
+  if (!b->cache_path.empty() && cache_apply(b, cache_lookup(b))) {
+    b->tuned = true;
+    return LOS_OK;
+  }
   int probe[2] = {b->nchunks / 2, b->nchunks - 1};
   if (b->nchunks > 1 && b->chunk_row0[b->nchunks] - b->chunk_row0[b->nchunks - 1] < b->kc)
     probe[1] = b->nchunks - 2;
@@ -290,6 +372,7 @@ int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
     }
   }
   b->tuned = true;
+  cache_store(b);
   return LOS_OK;
 }
 
@@ -310,6 +393,10 @@ int autotune(los_batch *b, const SolveArgs &s, hipStream_t st) {
     return LOS_OK;
   }
   if (!env_i("LOS_BATCH_TUNE", 1)) {
+    b->tuned = true;
+    return LOS_OK;
+  }
+  if (!b->cache_path.empty() && cache_apply(b, cache_lookup(b))) {
     b->tuned = true;
     return LOS_OK;
   }
@@ -365,6 +452,7 @@ int autotune(los_batch *b, const SolveArgs &s, hipStream_t st) {
     }
   }
   b->tuned = true;
+  cache_store(b);
   return LOS_OK;
 }
 
@@ -559,6 +647,12 @@ int los_batch_create(los_ctx *ctx, int32_t nmodels, int32_t nsrc, const int32_t 
   if (rc == LOS_OK) {
     hipError_t e = hipStreamCreate(&b->cap);
     if (e != hipSuccess) rc = hip_fail(e, "los_batch_create: stream");
+  }
+  if (rc == LOS_OK && los::ctx_tune_cache(ctx)) {
+    b->cache_path = los::ctx_tune_cache(ctx);
+    int mc = 0;
+    for (int v : b->chunk_maxcol) mc = std::max(mc, v);
+    b->cache_key = tune_key(b, mc);
   }
   if (rc != LOS_OK) {
     free_plan(b);

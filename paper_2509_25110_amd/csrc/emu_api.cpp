@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -83,6 +84,7 @@ struct los_emu {
   DevBuf lo, hi, mean, basis, basis_f, mean_f, sigma, tscale;
   DevBuf act, pre, gbuf, gbuf2, ub, zb, idx, part, loss;  // training / inference scratch
   DevBuf y, X, Om, Yq, Yt, G, Rinv, Zq, Bm, U, Vj, ev, cfs, zt, ut, st, yall, errb, cz;
+  DevBuf rows;  // emu_merge: the merged row indices
 };
 
 namespace {
@@ -584,6 +586,182 @@ int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *
   HIPCHK(E::ensemble(m->yall.as<float>(), m->members, n, (int)nl, m->tscale.as<double>(), cl,
                      m->errb.as<unsigned int>(), (float)threshold, err, need_fallback, s),
          "emu_infer: ensemble");
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- checkpoints
+//
+// File layout (host byte order), version 1:
+//   char magic[8] = "LOSEMU01"; uint32 version; int32 np, nl, ncomp, width,
+//   depth, members, 0; uint64 seed; int64 nparams; int32 has_pca; int32 0
+//   (64 bytes);
+//   float theta[members][nparams], adam_m[...], adam_v[...];
+//   if has_pca: double lo[np], hi[np], mean[4][nl], basis[4][nl][ncomp],
+//               sigma[4][ncomp], te_scale[nl];
+//   uint64 FNV-1a hash of every byte before it.
+
+namespace {
+
+constexpr char kEmuMagic[8] = {'L', 'O', 'S', 'E', 'M', 'U', '0', '1'};
+constexpr uint32_t kEmuVersion = 1;
+
+struct EmuHeader {  // 64 bytes, no implicit padding
+  char magic[8];
+  uint32_t version;
+  int32_t np, nl, ncomp, width, depth, members;
+  int32_t pad0;
+  uint64_t seed;
+  int64_t nparams;
+  int32_t has_pca, reserved;
+};
+static_assert(sizeof(EmuHeader) == 64, "checkpoint header layout");
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+  const unsigned char *c = (const unsigned char *)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 0x100000001B3ull;
+  }
+  return h;
+}
+
+// The device arrays of a checkpoint, in file order: (buffer, bytes).
+std::vector<std::pair<void *, size_t>> emu_sections(const los_emu *m) {
+  const size_t P = (size_t)m->nparams * m->members, nl = m->nl, nc = m->ncomp;
+  std::vector<std::pair<void *, size_t>> v = {{m->theta.p, sizeof(float) * P},
+                                              {m->adam_m.p, sizeof(float) * P},
+                                              {m->adam_v.p, sizeof(float) * P}};
+  if (m->has_pca) {
+    v.push_back({m->lo.p, sizeof(double) * m->np});
+    v.push_back({m->hi.p, sizeof(double) * m->np});
+    v.push_back({m->mean.p, sizeof(double) * 4 * nl});
+    v.push_back({m->basis.p, sizeof(double) * 4 * nl * nc});
+    v.push_back({m->sigma.p, sizeof(double) * 4 * nc});
+    v.push_back({m->tscale.p, sizeof(double) * nl});
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int emu_save(const los_emu *emu, const char *path, void *stream) {
+  if (!emu || !path) return fail(LOS_ERR_INVALID, "emu_save: NULL argument");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream), "emu_save: stream");
+  EmuHeader h{};
+  std::memcpy(h.magic, kEmuMagic, 8);
+  h.version = kEmuVersion;
+  h.np = emu->np;
+  h.nl = emu->nl;
+  h.ncomp = emu->ncomp;
+  h.width = emu->width;
+  h.depth = emu->depth;
+  h.members = emu->members;
+  h.seed = emu->seed;
+  h.nparams = emu->nparams;
+  h.has_pca = emu->has_pca ? 1 : 0;
+  std::vector<char> buf(sizeof h);
+  std::memcpy(buf.data(), &h, sizeof h);
+  for (const auto &sec : emu_sections(emu)) {
+    const size_t at = buf.size();
+    buf.resize(at + sec.second);
+    HIPCHK(hipMemcpy(buf.data() + at, sec.first, sec.second, hipMemcpyDeviceToHost),
+           "emu_save: copy");
+  }
+  const uint64_t hash = fnv1a(0xCBF29CE484222325ull, buf.data(), buf.size());
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(LOS_ERR_INVALID, "emu_save: cannot open %s for writing", path);
+  const bool okw = std::fwrite(buf.data(), 1, buf.size(), f) == buf.size() &&
+                   std::fwrite(&hash, sizeof hash, 1, f) == 1;
+  const bool okc = std::fclose(f) == 0;
+  if (!okw || !okc) return fail(LOS_ERR_INVALID, "emu_save: write to %s failed", path);
+  return ok();
+}
+
+int emu_load(los_ctx *ctx, const char *path, los_emu **out) {
+  if (!out) return fail(LOS_ERR_INVALID, "emu_load: out is NULL");
+  *out = nullptr;
+  if (!ctx || !path) return fail(LOS_ERR_INVALID, "emu_load: NULL argument");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(LOS_ERR_INVALID, "emu_load: cannot open %s", path);
+  std::vector<char> buf;
+  char tmp[1 << 16];
+  size_t got;
+  while ((got = std::fread(tmp, 1, sizeof tmp, f)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+  std::fclose(f);
+  EmuHeader h{};
+  if (buf.size() < sizeof h + sizeof(uint64_t))
+    return fail(LOS_ERR_INVALID, "emu_load: %s is too short to be an emulator file", path);
+  std::memcpy(&h, buf.data(), sizeof h);
+  if (std::memcmp(h.magic, kEmuMagic, 8) != 0)
+    return fail(LOS_ERR_INVALID, "emu_load: %s is not an emulator file", path);
+  if (h.version != kEmuVersion)
+    return fail(LOS_ERR_UNSUPPORTED, "emu_load: %s has version %u (this library reads %u)", path,
+                h.version, kEmuVersion);
+  uint64_t hash;
+  std::memcpy(&hash, buf.data() + buf.size() - sizeof hash, sizeof hash);
+  if (fnv1a(0xCBF29CE484222325ull, buf.data(), buf.size() - sizeof hash) != hash)
+    return fail(LOS_ERR_INVALID, "emu_load: %s is corrupt (checksum mismatch)", path);
+  los_emu *m = nullptr;
+  int rc = emu_create(ctx, h.np, h.nl, h.ncomp, h.width, h.depth, h.members, h.seed, &m);
+  if (rc != LOS_OK) return rc;
+  if (m->nparams != h.nparams) {
+    emu_destroy(m);
+    return fail(LOS_ERR_INVALID, "emu_load: %s holds %lld parameters per member, the shape "
+                "gives %lld", path, (long long)h.nparams, (long long)m->nparams);
+  }
+  m->has_pca = h.has_pca != 0;
+  size_t at = sizeof h;
+  const auto secs = emu_sections(m);
+  size_t need = at + sizeof hash;
+  for (const auto &sec : secs) need += sec.second;
+  if (need != buf.size()) {
+    emu_destroy(m);
+    return fail(LOS_ERR_INVALID, "emu_load: %s has %zu bytes, its header implies %zu", path,
+                buf.size(), need);
+  }
+  for (const auto &sec : secs) {
+    hipError_t e = hipMemcpy(sec.first, buf.data() + at, sec.second, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      emu_destroy(m);
+      return hip_fail(e, "emu_load: copy");
+    }
+    at += sec.second;
+  }
+  if (m->has_pca && (rc = refresh_float_pca(m, nullptr)) != LOS_OK) {
+    emu_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return ok();
+}
+
+int emu_merge(los_emu *emu, const int64_t *rows, int64_t nf, const double *cl_solved, double *cl,
+              int64_t n, float *err, uint8_t *need_fallback, void *stream) {
+  if (!emu || nf < 0 || n < 1) return fail(LOS_ERR_INVALID, "emu_merge: bad argument");
+  if (nf == 0) return ok();
+  if (!rows || !cl_solved || !cl) return fail(LOS_ERR_INVALID, "emu_merge: NULL array");
+  if (nf > n) return fail(LOS_ERR_INVALID, "emu_merge: nf = %lld > n = %lld", (long long)nf,
+                          (long long)n);
+  std::vector<char> seen((size_t)n, 0);
+  for (int64_t i = 0; i < nf; ++i) {
+    if (rows[i] < 0 || rows[i] >= n)
+      return fail(LOS_ERR_INVALID, "emu_merge: rows[%lld] = %lld out of [0, %lld)", (long long)i,
+                  (long long)rows[i], (long long)n);
+    if (seen[(size_t)rows[i]]++)
+      return fail(LOS_ERR_INVALID, "emu_merge: row %lld given twice", (long long)rows[i]);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = emu->rows.reserve(sizeof(int64_t) * (size_t)nf);
+  if (rc != LOS_OK) return rc;
+  HIPCHK(hipMemcpyAsync(emu->rows.p, rows, sizeof(int64_t) * (size_t)nf, hipMemcpyHostToDevice, s),
+         "emu_merge: rows");
+  HIPCHK(E::merge_rows(emu->rows.as<int64_t>(), nf, cl_solved, 4 * (int64_t)emu->nl, cl, err,
+                       need_fallback, s),
+         "emu_merge: launch");
   return ok();
 }
 

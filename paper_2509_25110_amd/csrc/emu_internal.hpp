@@ -65,6 +65,10 @@ hipError_t unwhiten(const float *out, int64_t n, int ncomp, int s_idx, int nout,
 hipError_t ensemble(const float *y, int members, int64_t n, int nl, const double *t, double *cl,
                     unsigned int *err_bits, float thr, float *err, unsigned char *flag,
                     hipStream_t s);
+// cl[rows[i]][*] = src[i][*] (row_len values each), err[rows[i]] = 0, flag[rows[i]] = 0
+// (err, flag may be NULL); rows in [0, n) and distinct (checked by the caller).
+hipError_t merge_rows(const int64_t *rows, int64_t nf, const double *src, int64_t row_len,
+                      double *cl, float *err, unsigned char *flag, hipStream_t s);
 
 }  // namespace emu
 }  // namespace los

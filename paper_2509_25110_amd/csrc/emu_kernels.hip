@@ -561,5 +561,34 @@ hipError_t ensemble(const float *y, int members, int64_t n, int nl, const double
   return hipGetLastError();
 }
 
+// Fallback merge: row rows[i] of cl [n][row_len] takes src[i][row_len]; its
+// error estimate becomes 0 and its fallback flag 0 (err, flag optional).
+__global__ __launch_bounds__(256) void merge_rows_kernel(const int64_t *rows, int64_t nf,
+                                                         const double *src, int64_t row_len,
+                                                         double *cl, float *err,
+                                                         unsigned char *flag) {
+  const int64_t total = nf * row_len;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / row_len, c = t - i * row_len;
+    const int64_t r = rows[i];
+    cl[r * row_len + c] = src[t];
+    if (c == 0) {
+      if (err) err[r] = 0.f;
+      if (flag) flag[r] = 0;
+    }
+  }
+}
+
+hipError_t merge_rows(const int64_t *rows, int64_t nf, const double *src, int64_t row_len,
+                      double *cl, float *err, unsigned char *flag, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  int64_t b = (nf * row_len + 255) / 256;
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(merge_rows_kernel, dim3((unsigned)b), dim3(256), 0, s, rows, nf, src, row_len,
+                     cl, err, flag);
+  return hipGetLastError();
+}
+
 }  // namespace emu
 }  // namespace los

@@ -22,6 +22,7 @@ enum { WS_CL = 0, WS_JTAB = 1, WS_SPLINE = 2, WS_LSEL = 3, WS_CLI = 4, WS_TENSOR
 
 struct los_ctx {
   int device = 0;
+  std::string tune_cache;   // batch autotune cache file ("" = none)
   void *scratch = nullptr;  // device address of `scratch` on this device (cl_integrate_noalloc)
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};
@@ -44,6 +45,10 @@ constexpr size_t kScratchBytes = (size_t)16 << 20;
 static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 namespace los {
+
+const char *ctx_tune_cache(const los_ctx *ctx) {
+  return ctx && !ctx->tune_cache.empty() ? ctx->tune_cache.c_str() : nullptr;
+}
 
 int fail(int code, const char *fmt, ...) {
   char buf[512];
@@ -268,7 +273,7 @@ const char *los_last_error(void) { return g_err.c_str(); }
 
 const char *los_version(void) { return "los-mi355x 0.1 (gfx950)"; }
 
-int los_ctx_create(los_ctx **ctx) {
+int los_ctx_create(los_ctx **ctx, const char *tune_cache_path) {
   if (!ctx) return fail(LOS_ERR_INVALID, "los_ctx_create: ctx is NULL");
   *ctx = nullptr;
   int dev = 0;
@@ -281,6 +286,7 @@ int los_ctx_create(los_ctx **ctx) {
   if (!c) return fail(LOS_ERR_OOM, "los_ctx_create: out of host memory");
   c->device = dev;
   c->scratch = sp;
+  if (tune_cache_path) c->tune_cache = tune_cache_path;
   *ctx = c;
   return ok();
 }

@@ -41,7 +41,7 @@ EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
            "los_batch_destroy",
            "emu_create", "emu_destroy", "emu_nparams", "emu_get_params", "emu_set_params",
            "emu_get_pca", "emu_set_pca", "emu_forward", "emu_loss_grad", "emu_fit", "emu_train",
-           "emu_infer")
+           "emu_infer", "emu_merge", "emu_save", "emu_load")
 
 
 class LosError(RuntimeError):
@@ -61,7 +61,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.los_version.restype = ctypes.c_char_p
     lib.los_version.argtypes = []
     lib.los_ctx_create.restype = ctypes.c_int
-    lib.los_ctx_create.argtypes = [ctypes.POINTER(vp)]
+    lib.los_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_char_p]
     lib.los_ctx_destroy.restype = None
     lib.los_ctx_destroy.argtypes = [vp]
     lib.los_bessel_table.restype = ctypes.c_int
@@ -115,6 +115,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "emu_fit": [vp, i32, vp, vp, i64, i32, i32, dbl, vp, vp],
         "emu_train": [vp, vp, vp, vp, vp, i64, i32, i32, dbl, vp, vp],
         "emu_infer": [vp, vp, i64, vp, vp, vp, dbl, vp],
+        "emu_merge": [vp, vp, i64, vp, vp, i64, vp, vp, vp],
+        "emu_save": [vp, ctypes.c_char_p, vp],
+        "emu_load": [vp, ctypes.c_char_p, ctypes.POINTER(vp)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -163,11 +166,13 @@ def _need(t: torch.Tensor, dtype, numel: int, name: str):
 
 
 class Context:
-    """A los_ctx (device workspace owner) bound to the current device."""
+    """A los_ctx (device workspace owner) bound to the current device; tune_cache (a file
+    path) keeps the batch autotuner's choices across processes."""
 
-    def __init__(self):
+    def __init__(self, tune_cache: Optional[str] = None):
         h = ctypes.c_void_p()
-        _check(lib().los_ctx_create(ctypes.byref(h)))
+        _check(lib().los_ctx_create(ctypes.byref(h),
+                                    os.fsencode(tune_cache) if tune_cache else None))
         self._h = h
 
     @property
@@ -368,12 +373,16 @@ class Emulator:
     """A los_emu (entry points emu_*): ensemble MLP emulator of the 4 spectra."""
 
     def __init__(self, ctx: Context, nparam: int, nl: int, ncomp: int = 96, width: int = 512,
-                 depth: int = 4, members: int = 4, seed: int = 1):
-        h = ctypes.c_void_p()
-        _check(lib().emu_create(ctx.handle, nparam, nl, ncomp, width, depth, members, seed,
-                                ctypes.byref(h)))
+                 depth: int = 4, members: int = 4, seed: int = 1, _handle=None):
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib().emu_create(ctx.handle, nparam, nl, ncomp, width, depth, members, seed,
+                                    ctypes.byref(h)))
+        else:
+            h = _handle
         self._h = h
         self.nparam, self.nl, self.ncomp, self.members = nparam, nl, ncomp, members
+        self.width, self.depth, self.seed = width, depth, seed
         self.nout = 4 * ncomp
         n = ctypes.c_int64()
         _check(lib().emu_nparams(h, ctypes.byref(n)))
@@ -460,6 +469,40 @@ class Emulator:
         _check(lib().emu_infer(self._h, _ptr(params), n, _ptr(cl), _ptr(err), _ptr(flag),
                                float(threshold), _stream(stream)))
         return cl, err, flag
+
+    def emu_merge(self, rows, cl_solved: torch.Tensor, cl: torch.Tensor, err=None, flag=None,
+                  stream=None):
+        """Replace rows `rows` (host ints) of an emu_infer result by re-solved spectra
+        cl_solved [len(rows), 4, nl] (float64, device); their err and flag become 0."""
+        import numpy as np
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        n = cl.shape[0]
+        _need(cl, torch.float64, n * 4 * self.nl, "cl")
+        if r.size:
+            _need(cl_solved, torch.float64, r.size * 4 * self.nl, "cl_solved")
+        if err is not None:
+            _need(err, torch.float32, n, "err")
+        if flag is not None:
+            _need(flag, torch.uint8, n, "flag")
+        _check(lib().emu_merge(self._h, r.ctypes.data, r.size, _ptr(cl_solved) if r.size else None,
+                               _ptr(cl), n, _ptr(err), _ptr(flag), _stream(stream)))
+        return cl
+
+    def emu_save(self, path: str, stream=None):
+        _check(lib().emu_save(self._h, os.fsencode(path), _stream(stream)))
+
+    @classmethod
+    def emu_load(cls, ctx: Context, path: str) -> "Emulator":
+        """An emulator created from a file written by emu_save; its shape is read from the
+        file."""
+        import struct
+        h = ctypes.c_void_p()
+        _check(lib().emu_load(ctx.handle, os.fsencode(path), ctypes.byref(h)))
+        with open(path, "rb") as f:
+            head = f.read(64)  # the header: magic, version, 6 shape ints, pad, seed, ...
+        np_, nl, ncomp, width, depth, members = struct.unpack("<6i", head[12:36])
+        seed = struct.unpack("<Q", head[40:48])[0]
+        return cls(ctx, np_, nl, ncomp, width, depth, members, seed, _handle=h)
 
     def emu_destroy(self):
         if self._h is not None and self._h.value:

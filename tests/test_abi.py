@@ -58,7 +58,7 @@ def test_null_context_rejected(lib):
     assert rc == 1 and b"ctx" in lib.los_last_error()
     rc = lib.los_bessel_table(None, None, 1, 0, 3, None, None)
     assert rc == 1
-    rc = lib.los_ctx_create(None)
+    rc = lib.los_ctx_create(None, None)
     assert rc == 1
 
 

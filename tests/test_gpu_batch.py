@@ -228,6 +228,36 @@ def test_batch_one_model_matches_projection(torch_dev, ctx):
     plan.close()
 
 
+def test_batch_tune_cache(torch_dev, tmp_path):
+    """A context with a tune cache: the first plan tunes and appends its choice; a plan of the
+    same shape in another context reads it back (no second tuning line) and solves the same."""
+    from paper_2509_25110_amd import los
+    path = str(tmp_path / "tune.txt")
+    b = small_batch(n=8, seed=9)
+    c1 = los.Context(tune_cache=path)
+    plan, S, cl1 = solve(torch_dev, c1, b, 2)
+    info1 = plan.los_batch_info()
+    assert info1["tuned"] == 1
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and "fused" in lines[0] and "shape=" in lines[0], lines
+    plan.close()
+    c1.close()
+    c2 = los.Context(tune_cache=path)
+    plan2, _, cl2 = solve(torch_dev, c2, b, 2, S=S)
+    assert plan2.los_batch_info()["fused_shape"] == info1["fused_shape"]
+    assert len(open(path).read().splitlines()) == 1
+    np.testing.assert_array_equal(cl2, cl1)
+    # a foreign or damaged line is ignored: the plan tunes again and appends a line
+    with open(path, "w") as f:
+        f.write(lines[0].rsplit(" ", 1)[0] + " shape=99\n")
+    plan2.close()
+    plan3, _, cl3 = solve(torch_dev, c2, b, 2, S=S)
+    assert len(open(path).read().splitlines()) == 2
+    np.testing.assert_array_equal(cl3, cl1)
+    plan3.close()
+    c2.close()
+
+
 def test_batch_invalid_arguments(torch_dev, ctx):
     from paper_2509_25110_amd import los
     b = small_batch(n=2)

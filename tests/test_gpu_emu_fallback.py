@@ -1,0 +1,186 @@
+"""The emulator's checkpoint files (emu_save / emu_load) and its fallback to the plain solve
+(emu_infer -> los_batch_solve of the flagged models -> emu_merge), through the C ABI.
+
+* round trip: an emulator loaded from a file infers bitwise what the saved one inferred, and
+  holds the same parameters and tables; truncated, corrupted and foreign files are refused;
+* merge: the merged rows are exactly the re-solved spectra, their estimate and flag become 0,
+  the other rows are untouched; bad row lists are refused before anything is launched;
+* end to end at the configured threshold (1e-3): every flagged model's spectra become the plain
+  solve's (to the rounding of a different k-sum chunking, 1e-12), the unflagged ones stay the
+  emulator's, and the run reports the fallback fraction and the time per spectrum of
+  emulate + fall back against solving everything."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_2509_25110_amd import los
+    c = los.Context()
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def seeded_emulator(ctx, rng, nl=60, ncomp=8, width=48, depth=2, members=3, seed=11):
+    """An emulator with host-made PCA tables and weights (no training needed)."""
+    from paper_2509_25110_amd import los
+    emu = los.Emulator(ctx, 5, nl, ncomp=ncomp, width=width, depth=depth, members=members,
+                       seed=seed)
+    mean = np.stack([np.linspace(-20, -22, nl), np.linspace(-24, -25, nl), np.zeros(nl),
+                     np.linspace(-19, -21, nl)])
+    basis = np.linalg.qr(rng.standard_normal((4, nl, ncomp)))[0]
+    sigma = np.repeat(rng.uniform(0.05, 0.2, size=(4, 1)), ncomp, axis=1)
+    emu.emu_set_pca(-np.ones(5), np.ones(5), mean, basis, sigma, np.full(nl, 1e-11))
+    for e in range(members):
+        emu.emu_set_params(e, (rng.standard_normal(emu.nparams) * 0.05).astype(np.float32))
+    return emu
+
+
+def test_emu_save_load_roundtrip(torch_dev, ctx, tmp_path):
+    from paper_2509_25110_amd import los
+    torch = torch_dev
+    rng = np.random.default_rng(3)
+    emu = seeded_emulator(ctx, rng)
+    q = dev(torch, rng.uniform(-1, 1, size=(77, 5)))
+    c0, e0, f0 = emu.emu_infer(q, threshold=1e-3)
+    path = str(tmp_path / "emu.bin")
+    emu.emu_save(path)
+    emu2 = los.Emulator.emu_load(ctx, path)
+    assert (emu2.nl, emu2.ncomp, emu2.members, emu2.nparams) == (emu.nl, emu.ncomp, emu.members,
+                                                                 emu.nparams)
+    c1, e1, f1 = emu2.emu_infer(q, threshold=1e-3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(c1.cpu().numpy(), c0.cpu().numpy())
+    np.testing.assert_array_equal(e1.cpu().numpy(), e0.cpu().numpy())
+    np.testing.assert_array_equal(f1.cpu().numpy(), f0.cpu().numpy())
+    for m in range(emu.members):
+        np.testing.assert_array_equal(emu2.emu_get_params(m), emu.emu_get_params(m))
+    p0, p1 = emu.emu_get_pca(), emu2.emu_get_pca()
+    for key in p0:
+        np.testing.assert_array_equal(p1[key], p0[key])
+    emu2.close()
+    raw = open(path, "rb").read()
+    bad = tmp_path / "bad.bin"
+    for blob in (raw[:-9], raw[:40], raw[:200] + bytes([raw[200] ^ 1]) + raw[201:],
+                 b"NOTANEMU" + raw[8:]):
+        bad.write_bytes(blob)
+        with pytest.raises(los.LosError):
+            los.Emulator.emu_load(ctx, str(bad))
+    with pytest.raises(los.LosError):
+        los.Emulator.emu_load(ctx, str(tmp_path / "missing.bin"))
+    emu.close()
+
+
+def test_emu_merge_rows(torch_dev, ctx):
+    from paper_2509_25110_amd import los
+    torch = torch_dev
+    rng = np.random.default_rng(5)
+    emu = seeded_emulator(ctx, rng)
+    n = 40
+    q = dev(torch, rng.uniform(-1, 1, size=(n, 5)))
+    c, err, flag = emu.emu_infer(q, threshold=0.0)   # every row flagged
+    before = c.cpu().numpy().copy()
+    rows = np.array([3, 0, 39, 17], dtype=np.int64)
+    solved = rng.standard_normal((rows.size, 4, emu.nl))
+    emu.emu_merge(rows, dev(torch, solved), c, err=err, flag=flag)
+    torch.cuda.synchronize()
+    after, e, f = c.cpu().numpy(), err.cpu().numpy(), flag.cpu().numpy()
+    np.testing.assert_array_equal(after[rows], solved)
+    keep = np.setdiff1d(np.arange(n), rows)
+    np.testing.assert_array_equal(after[keep], before[keep])
+    assert np.all(e[rows] == 0) and np.all(f[rows] == 0) and np.all(f[keep] == 1)
+    emu.emu_merge([], None, c)                       # nothing to merge: no-op
+    for bad in ([0, 0], [-1], [n]):
+        with pytest.raises(los.LosError):
+            emu.emu_merge(bad, dev(torch, np.zeros((len(bad), 4, emu.nl))), c)
+    emu.close()
+
+
+def test_emu_fallback_end_to_end(torch_dev, ctx):
+    """Small grids (l <= 200, 120 master k, 400 tau): train on 1024 batch-solver spectra,
+    emulate 256 held-out draws at the configured threshold 1e-3, re-solve the flagged ones with
+    the batched solver and merge."""
+    torch = torch_dev
+    from paper_2509_25110_amd import inputs
+
+    def solve(draws):
+        b = inputs.batch_inputs(draws, ntau=400, master_nk=120, master_kmax=0.06)
+        plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
+                                    prec=2)
+        col, ncols = plan.los_batch_columns()
+        S = dev(torch, inputs.batch_sources_host(b, col, ncols))
+        args = (b.tau0, dev(torch, b.k_master), dev(torch, b.tau), dev(torch, b.w_tau), S,
+                dev(torch, b.w_lnk), dev(torch, b.Pk))
+        plan.los_batch_solve(*args)                  # plan tuning and graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cl = plan.los_batch_solve(*args)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.close()
+        return cl, dt
+
+    def params(draws):
+        return np.array([[d.tau_star, d.width, d.a_isw, d.n_s, d.ln1e10As] for d in draws])
+
+    pin = dict(lmax_range=(200, 200), nk_range=(120, 120))
+    tr = inputs.draw_models(1024, seed=1, **pin)
+    te = inputs.draw_models(256, seed=2, **pin)
+    ctr, _ = solve(tr)
+    cte, solve_all_s = solve(te)
+    lo = np.array([260.0, 15.0, 0.0, 0.92, 2.9])
+    hi = np.array([300.0, 25.0, 0.2, 1.0, 3.2])
+    from paper_2509_25110_amd import los
+    emu = los.Emulator(ctx, 5, ctr.shape[2], ncomp=24, width=128, depth=3, members=4, seed=5)
+    emu.emu_train(dev(torch, params(tr)), lo, hi, ctr, epochs=300, batch=128, lr=2e-3)
+    thr = 1e-3
+    P = dev(torch, params(te))
+    emu.emu_infer(P, threshold=thr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, err, flag = emu.emu_infer(P, threshold=thr)
+    fl = flag.cpu().numpy()                          # the host needs the list to plan a solve
+    rows = np.nonzero(fl)[0]
+    emu_c = c.cpu().numpy()
+    t_emu = time.perf_counter() - t0
+    t_fb = 0.0
+    if rows.size:
+        cfb, t_fb = solve([te[i] for i in rows])
+        emu.emu_merge(rows, cfb, c, err=err, flag=flag)
+    torch.cuda.synchronize()
+    got, ref = c.cpu().numpy(), cte.cpu().numpy()
+    assert not np.any(flag.cpu().numpy())
+    scale = np.abs(ref).copy()
+    scale[:, 2] = np.sqrt(ref[:, 0] * ref[:, 1])
+    rel = np.max(np.abs(got - ref) / scale, axis=(1, 2))
+    if rows.size:
+        assert np.max(rel[rows]) <= 1e-12, np.max(rel[rows])
+    keep = np.setdiff1d(np.arange(len(te)), rows)
+    np.testing.assert_array_equal(got[keep], emu_c[keep])
+    frac = rows.size / len(te)
+    per_emulated = (t_emu + t_fb) / len(te)
+    per_solve = solve_all_s / len(te)
+    print("fallback at %.0e: %d/%d flagged (%.2f); unflagged true error median %.2e max %.2e; "
+          "emulate + fall back %.2f us per spectrum vs solve %.2f us (gain %.2fx)"
+          % (thr, rows.size, len(te), frac,
+             float(np.median(rel[keep])) if keep.size else float("nan"),
+             float(np.max(rel[keep])) if keep.size else float("nan"),
+             per_emulated * 1e6, per_solve * 1e6, per_solve / per_emulated))
+    emu.close()
