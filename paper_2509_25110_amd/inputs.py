@@ -357,3 +357,34 @@ def batch_sources_device(b: BatchInputs, col: np.ndarray, S_packed, torch) -> No
         S_packed[rows] = (g * (1.0 + 0.3 * torch.cos(150.0 * k)) + d.a_isw * late[None, :]).float()
         S_packed[rows + 1] = (0.5 * k * k * g).float()
         S_packed[rows + 2] = lens[None, :].expand(hi - lo, -1).float()
+
+
+def model_sources_device(wl: Workload, torch, device="cuda"):
+    """The sources S[3, nk, ntau] float64 of a drawn model's workload (model_workload(d,
+    ...) built with S omitted is enough: k, tau and the draw's parameters), evaluated by torch
+    on the device with the formulas of `sources` (host generation of a full-grid model is
+    slow)."""
+    p = wl.params
+    tau = torch.from_numpy(wl.tau).to(device)
+    k = torch.from_numpy(wl.k).to(device)[:, None]
+    g = torch.exp(-((tau - p["tau_star"]) ** 2) / (2.0 * p["width"] * p["width"]))[None, :]
+    late = torch.exp(-((tau - 12000.0) ** 2) / (2.0 * 1500.0 ** 2))[None, :]
+    S = torch.empty((3, wl.k.size, wl.tau.size), dtype=torch.float64, device=device)
+    S[0] = g * (1.0 + 0.3 * torch.cos(150.0 * k)) + p["a_isw"] * late
+    S[1] = 0.5 * k * k * g
+    S[2] = torch.from_numpy(lensing_kernel(wl.tau)).to(device)[None, :]
+    return S
+
+
+def model_grid(d: ModelDraw, ntau: int = 3000, master_nk: int = MASTER_NK,
+               master_kmax: float = MASTER_KMAX, kmin: float = 1e-4) -> Workload:
+    """model_workload without the host sources (S is None): grids, weights and P(k)."""
+    kmaster = log_k_grid(master_nk, kmin, master_kmax)
+    k = kmaster[master_indices(d.nk, master_nk)]
+    tau = tau_grid(ntau)
+    return Workload(name="model", lmin=2, lmax=d.lmax, k=k, tau=tau, tau0=TAU0,
+                    w_tau=trapezoid_weights(tau), w_lnk=trapezoid_weights(np.log(k)),
+                    Pk=primordial(k, d.A_s, d.n_s), S=None, pairs=PAIRS_4,
+                    pair_names=PAIR_NAMES_4,
+                    params=dict(A_s=d.A_s, n_s=d.n_s, tau_star=d.tau_star, width=d.width,
+                                a_isw=d.a_isw))
