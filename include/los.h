@@ -30,6 +30,11 @@
  *   - A los_ctx owns the library's device workspace (grown on demand and
  *     reused).  A context is not thread-safe: use one per host thread, and do
  *     not run two calls of one context concurrently on different streams.
+ *   - Result check: with the environment variable LOS_CHECK_FINITE=1, the
+ *     entry points that write spectra, transfer functions or Bessel tables
+ *     (all but cl_integrate_noalloc) scan their output on the device after
+ *     enqueueing, wait for the stream, and return LOS_ERR_NUMERIC if any value
+ *     is NaN or infinite (the output is still written).  Off by default.
  *   - Floating point: FP64 entry points compute in IEEE double; results agree
  *     with a plain FP64 evaluation of the formulas above to about 1e-12
  *     (normwise); entries smaller than ~1e-20 of the local peak of j_l are
@@ -50,7 +55,7 @@ typedef enum {
     LOS_ERR_HIP = 2,         /* HIP runtime or launch failure                */
     LOS_ERR_OOM = 3,         /* device workspace allocation failed           */
     LOS_ERR_UNSUPPORTED = 4, /* valid request outside what is implemented    */
-    LOS_ERR_NUMERIC = 5      /* reserved: non-finite result detected         */
+    LOS_ERR_NUMERIC = 5      /* non-finite result (only with LOS_CHECK_FINITE) */
 } los_status;
 
 typedef enum {

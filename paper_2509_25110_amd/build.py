@@ -28,7 +28,7 @@ SOURCES = ["project_fp64_desc_n3.hip", "project_fp64_desc_n4.hip", "project_fp64
            "emu_kernels.hip", "project_fused.hip", "project_mfma.hip", "project_mfma_lds.hip",
            "spline.hip", "los_api.cpp", "batch_api.cpp", "emu_api.cpp", "bessel_table.hip",
            "project_fp64_desc.hip", "cl_reduce.hip", "jtable.hip", "batch_cl.hip", "cl_interp.hip",
-           "tensor.hip"]
+           "tensor.hip", "finite_check.hip"]
 # host build of the Bessel seed functions, for CPU checks (not linked into liblos.so)
 HOSTCHECK_SRC = "bessel_host_check.cpp"
 HOSTCHECK_LIB = os.path.join(PKG, "liblos_hostcheck.so")

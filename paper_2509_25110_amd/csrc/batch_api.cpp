@@ -699,6 +699,9 @@ int los_batch_solve(los_batch *plan, double tau0, const double *k_master, const 
   }
   if (!env_i("LOS_BATCH_GRAPH", 1)) {
     int rc = enqueue(plan, s, st);
+    if (rc == LOS_OK)
+      rc = los::check_result("los_batch_solve", cl,
+                             (int64_t)plan->nmodels * plan->npairs * plan->nl, false, st);
     return rc == LOS_OK ? ok() : rc;
   }
   const void *key[9] = {k_master, tau, w_tau, S_packed, w_lnk, Pk, cl, nullptr, nullptr};
@@ -730,7 +733,9 @@ int los_batch_solve(los_batch *plan, double tau0, const double *k_master, const 
   }
   hipError_t e = hipGraphLaunch(plan->exec, st);
   if (e != hipSuccess) return hip_fail(e, "los_batch_solve: graph launch");
-  return ok();
+  const int rc = los::check_result("los_batch_solve", cl,
+                                   (int64_t)plan->nmodels * plan->npairs * plan->nl, false, st);
+  return rc == LOS_OK ? ok() : rc;
 }
 
 int los_batch_solve_timed(los_batch *plan, double tau0, const double *k_master,

@@ -586,7 +586,8 @@ int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *
   HIPCHK(E::ensemble(m->yall.as<float>(), m->members, n, (int)nl, m->tscale.as<double>(), cl,
                      m->errb.as<unsigned int>(), (float)threshold, err, need_fallback, s),
          "emu_infer: ensemble");
-  return ok();
+  rc = los::check_result("emu_infer", cl, n * 4 * nl, false, s);
+  return rc == LOS_OK ? ok() : rc;
 }
 
 }  // extern "C"

@@ -69,6 +69,16 @@ int hip_fail(hipError_t e, const char *what) {
   return fail(LOS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+int check_result(const char *who, const void *p, int64_t n, bool f32, hipStream_t s) {
+  if (!finite_check_enabled()) return LOS_OK;
+  unsigned long long bad = 0;
+  hipError_t e = count_nonfinite(p, n, f32, s, &bad);
+  if (e != hipSuccess) return hip_fail(e, who);
+  if (bad)
+    return fail(LOS_ERR_NUMERIC, "%s: %llu of %lld results are not finite", who, bad, (long long)n);
+  return LOS_OK;
+}
+
 }  // namespace los
 
 namespace {
@@ -310,7 +320,9 @@ int los_bessel_table(los_ctx *ctx, const double *x, int64_t nx, int32_t lmin, in
   if (nx > (int64_t)1 << 40) return fail(LOS_ERR_INVALID, "los_bessel_table: nx too large");
   hipError_t e = los::bessel_table_launch(x, nx, lmin, lmax, out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "los_bessel_table launch");
-  return ok();
+  const int rc = los::check_result("los_bessel_table", out, nx * (int64_t)(lmax - lmin + 1), false,
+                                   (hipStream_t)stream);
+  return rc == LOS_OK ? ok() : rc;
 }
 
 int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau,
@@ -339,11 +351,17 @@ int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, in
     if (kernel_mask != 0)
       return fail(LOS_ERR_UNSUPPORTED, "los_project: the E-mode kernel is FP64 only");
     const char *fz = std::getenv("LOS_MIXED_FUSED");
-    if (fz && std::atoi(fz) == 0)
-      return project_mixed(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S,
-                           nsrc, prec, (float *)delta, (hipStream_t)stream);
-    return project_mixed_fused(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau, (const float *)S,
-                               nsrc, prec, (float *)delta, (hipStream_t)stream);
+    const bool tables = fz && std::atoi(fz) == 0;
+    int rc = tables ? project_mixed(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau,
+                                    (const float *)S, nsrc, prec, (float *)delta,
+                                    (hipStream_t)stream)
+                    : project_mixed_fused(ctx, lmin, lmax, nk, ntau, tau0, k, tau, w_tau,
+                                          (const float *)S, nsrc, prec, (float *)delta,
+                                          (hipStream_t)stream);
+    if (rc != LOS_OK) return rc;
+    rc = los::check_result("los_project", delta, nk * (int64_t)(lmax - lmin + 1) * nsrc, true,
+                           (hipStream_t)stream);
+    return rc == LOS_OK ? ok() : rc;
   }
 
   // Default: the single descending sweep; LOS_PROJ_SCHEME=0 selects the
@@ -381,7 +399,9 @@ int los_project_kernels(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, in
   hipError_t e = desc ? los::project_fp64_desc_launch(a, nsrc, sh, (hipStream_t)stream)
                       : los::project_fp64_launch(a, nsrc, sh, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "los_project launch");
-  return ok();
+  const int rc = los::check_result("los_project", delta, nk * (int64_t)a.nl * nsrc, false,
+                                   (hipStream_t)stream);
+  return rc == LOS_OK ? ok() : rc;
 }
 
 int los_project(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int64_t ntau, double tau0,
@@ -445,7 +465,8 @@ int los_project_tensor(los_ctx *ctx, int32_t lmin, int32_t lmax, int64_t nk, int
   if (e != hipSuccess) return hip_fail(e, "los_project_tensor: sweep launch");
   e = los::tensor_combine_launch((const double *)ws, delta, lmin, nl, nk, st);
   if (e != hipSuccess) return hip_fail(e, "los_project_tensor: combine launch");
-  return ok();
+  rc = los::check_result("los_project_tensor", delta, nk * (int64_t)nl * 3, false, st);
+  return rc == LOS_OK ? ok() : rc;
 }
 
 int los_project_lsample(los_ctx *ctx, int32_t lmin, int32_t lmax, const int32_t *ls,
@@ -536,7 +557,8 @@ int los_project_lsample(los_ctx *ctx, int32_t lmin, int32_t lmax, const int32_t 
   a.nls = nls;
   hipError_t e = los::project_fp64_desc_launch(a, nsrc, sh, st);
   if (e != hipSuccess) return hip_fail(e, "los_project_lsample launch");
-  return ok();
+  const int rc2 = los::check_result("los_project_lsample", delta, nk * (int64_t)nls * nsrc, false, st);
+  return rc2 == LOS_OK ? ok() : rc2;
 }
 
 }  // extern "C"
@@ -597,7 +619,8 @@ int cl_integrate(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t ns
   a.partial = (double *)ws;
   hipError_t e = los::cl_launch(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "cl_integrate launch");
-  return ok();
+  rc = los::check_result("cl_integrate", cl, (int64_t)npairs * nl, false, (hipStream_t)stream);
+  return rc == LOS_OK ? ok() : rc;
 }
 
 int cl_integrate_noalloc(los_ctx *ctx, const void *delta, int32_t delta_prec, int32_t nsrc,

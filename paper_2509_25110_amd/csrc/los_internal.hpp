@@ -182,6 +182,15 @@ hipError_t tensor_combine_launch(const double *d4, double *out, int lmin, int nl
 // The batch autotune cache file of a context (los_api.cpp), or nullptr.
 const char *ctx_tune_cache(const los_ctx *ctx);
 
+// Optional result check (finite_check.hip): enabled by LOS_CHECK_FINITE=1;
+// count_nonfinite scans n values (float or double) on stream s and waits.
+bool finite_check_enabled();
+// LOS_OK, or LOS_ERR_NUMERIC when the check is enabled and finds a non-finite
+// value among the n results (los_api.cpp).
+int check_result(const char *who, const void *p, int64_t n, bool f32, hipStream_t s);
+hipError_t count_nonfinite(const void *p, int64_t n, bool f32, hipStream_t s,
+                           unsigned long long *bad);
+
 // Error reporting shared by the C entry points (los_api.cpp).
 int fail(int code, const char *fmt, ...);
 int ok();

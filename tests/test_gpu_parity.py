@@ -327,3 +327,31 @@ def test_sweep_block8_small_vs_oracle(torch_dev, ctx, cfg, monkeypatch):
     cfg = dict(cfg)
     nsrc = cfg.pop("nsrc")
     check_workload(torch_dev, ctx, inputs.small(nsrc=min(nsrc, 3), **cfg))
+
+
+def test_check_finite_reports_nonfinite(torch_dev, ctx, monkeypatch):
+    """With LOS_CHECK_FINITE=1 a NaN in the sources gives LOS_ERR_NUMERIC from los_project and
+    from cl_integrate (results still written); finite inputs pass; unset, nothing is checked."""
+    from paper_2509_25110_amd import los
+    torch = torch_dev
+    wl = inputs.small(lmax=40, nk=6, kmax=0.02, ntau=200, nsrc=3)
+    args = [dev(torch, wl.k), dev(torch, wl.tau), wl.tau0, dev(torch, wl.w_tau)]
+    good = dev(torch, wl.S)
+    bad_S = wl.S.copy()
+    bad_S[1, 2, 50] = np.nan
+    bad = dev(torch, bad_S)
+    wk, Pk = dev(torch, wl.w_lnk), dev(torch, wl.Pk)
+    monkeypatch.setenv("LOS_CHECK_FINITE", "1")
+    d = ctx.los_project(wl.lmin, wl.lmax, *args, good)
+    ctx.cl_integrate(d, wk, Pk, wl.pairs)
+    with pytest.raises(los.LosError) as ei:
+        ctx.los_project(wl.lmin, wl.lmax, *args, bad)
+    assert ei.value.code == los.LOS_ERR_NUMERIC
+    dn = torch.empty_like(d)
+    dn.fill_(float("inf"))
+    with pytest.raises(los.LosError) as ei:
+        ctx.cl_integrate(dn, wk, Pk, wl.pairs)
+    assert ei.value.code == los.LOS_ERR_NUMERIC
+    monkeypatch.delenv("LOS_CHECK_FINITE")
+    ctx.los_project(wl.lmin, wl.lmax, *args, bad)   # unchecked: no error
+    torch.cuda.synchronize()
