@@ -28,16 +28,34 @@ __global__ __launch_bounds__(256) void batch_cl_kernel(BatchClArgs a) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
   const int64_t p0 = a.koff[m];
-  for (int64_t j = jlo; j < jhi; ++j) {
+  auto add_term = [&](const double wp, const double (&v)[NSRC]) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < a.npairs) acc[q] += wp * v[a.pa[q]] * v[a.pb[q]];
+  };
+  int64_t j = jlo;
+  // four k at a time: every load of the four issued before the first term is
+  // added; the terms are added in increasing j as in the plain loop
+  for (; j + 4 <= jhi; j += 4) {
+    double v[4][NSRC], wp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t p = p0 + j + u;
+      const float *d = a.D + (a.pos_col[p] - a.col_base) * (int64_t)a.nl + lr;
+#pragma unroll
+      for (int s = 0; s < NSRC; ++s) v[u][s] = (double)d[(int64_t)s * a.nl];
+      wp[u] = a.w_lnk[p] * a.Pk[p];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add_term(wp[u], v[u]);
+  }
+  for (; j < jhi; ++j) {
     const int64_t p = p0 + j;
     const float *d = a.D + (a.pos_col[p] - a.col_base) * (int64_t)a.nl + lr;
     double v[NSRC];
 #pragma unroll
     for (int s = 0; s < NSRC; ++s) v[s] = (double)d[(int64_t)s * a.nl];
-    const double wp = a.w_lnk[p] * a.Pk[p];
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (q < a.npairs) acc[q] += wp * v[a.pa[q]] * v[a.pb[q]];
+    add_term(a.w_lnk[p] * a.Pk[p], v);
   }
   const double four_pi = 12.566370614359172954;
   double *out = a.cl + (int64_t)m * a.npairs * a.nl + lr;

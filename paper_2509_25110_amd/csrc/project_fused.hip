@@ -332,14 +332,23 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
               const float *src = Jf + (wr * MBW * 16 + 16 * i + r16) * LD + kofs;
               const float4 u = *(const float4 *)src, v = *(const float4 *)(src + 4);
               const float af[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+              if (wr * MBW + i <= jlast[NBW - 1]) {  // every column block: accumulators in turn
 #pragma unroll
-              for (int j = 0; j < NBW; ++j)
-                if (wr * MBW + i <= jlast[j]) {
+                for (int e = 0; e < 8; ++e)
 #pragma unroll
-                  for (int e = 0; e < 8; ++e)
+                  for (int j = 0; j < NBW; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e], acc[i][j],
                                                                      0, 0, 0);
-                }
+              } else {
+#pragma unroll
+                for (int j = 0; j < NBW; ++j)
+                  if (wr * MBW + i <= jlast[j]) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e],
+                                                                       acc[i][j], 0, 0, 0);
+                  }
+              }
             }
           }
         } else {
@@ -356,13 +365,25 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
               const int row = wr * MBW * 16 + 16 * i + r16;
               const bf8 ah = *(const bf8 *)(Jh + row * LD + kofs);
               const bf8 al = *(const bf8 *)(Jl + row * LD + kofs);
+              if (wr * MBW + i <= jlast[NBW - 1]) {  // every column block: accumulators in turn
 #pragma unroll
-              for (int j = 0; j < NBW; ++j)
-                if (wr * MBW + i <= jlast[j]) {
+                for (int j = 0; j < NBW; ++j)
                   acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < NBW; ++j)
                   acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < NBW; ++j)
                   acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-                }
+              } else {
+#pragma unroll
+                for (int j = 0; j < NBW; ++j)
+                  if (wr * MBW + i <= jlast[j]) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+                  }
+              }
             }
           }
         }
