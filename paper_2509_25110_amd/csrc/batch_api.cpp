@@ -303,7 +303,7 @@ int enqueue(los_batch *b, const SolveArgs &s, hipStream_t st) {
   return LOS_OK;
 }
 
-// Fused pipeline: time the wide fused shapes (0..3) on two representative
+// Fused pipeline: time the wide fused shapes (0..3 and 6) on two representative
 // chunks after building their seeds once; keep the fastest total.
 // LOS_BATCH_SHAPE pins a shape; LOS_BATCH_TUNE=0 keeps shape 0.
 int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
@@ -335,7 +335,8 @@ int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
     (void)hipEventDestroy(t0);
     return hip_fail(e, "autotune: event");
   }
-  constexpr int kWide = 4;  // shapes 0..3 have at least 128 columns
+  constexpr int kWide = 5;  // the shapes with at least 128 columns
+  constexpr int wide[kWide] = {0, 1, 2, 3, 6};
   float total[kWide] = {};
   int rc = LOS_OK;
   for (int pi = 0; pi < nprobe && rc == LOS_OK; ++pi) {
@@ -351,7 +352,8 @@ int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
       float ms = 0.f;
       for (int rep = 0; rep < 2 && rc == LOS_OK; ++rep) {  // first run warms up
         e = hipEventRecord(t0, st);
-        if (e == hipSuccess) e = los::fused_gemm_launch(fa, b->prec, i, cnt, b->chunk_maxcol[c], st);
+        if (e == hipSuccess)
+          e = los::fused_gemm_launch(fa, b->prec, wide[i], cnt, b->chunk_maxcol[c], st);
         if (e == hipSuccess) e = hipEventRecord(t1, st);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
@@ -365,10 +367,10 @@ int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
   if (rc != LOS_OK) return rc;
   float best = 1e30f;
   for (int i = 0; i < kWide; ++i) {
-    b->ftune_ms[i] = total[i];
+    b->ftune_ms[wide[i]] = total[i];
     if (total[i] < best) {
       best = total[i];
-      b->fshape = i;
+      b->fshape = wide[i];
     }
   }
   b->tuned = true;

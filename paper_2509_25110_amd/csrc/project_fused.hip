@@ -128,315 +128,519 @@ struct LdsLayout<2> {  // bf16 hi and lo rows of KB + 8 (144 bytes: 16 rows hit 
 
 __device__ inline u16 bf16_bits(__bf16 v) { return __builtin_bit_cast(u16, v); }
 
-template <int PREC, int WR, int WC, int MBW, int NBW>
-__global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, int tiles_m,
-                                                                  int tiles_n, int kcount) {
-  constexpr int NT = 64 * WR * WC;
-  constexpr int TM = WR * MBW * 16, TN = WC * NBW * 16;
-  constexpr int NSEG = TM / 32;
-  static_assert(NSEG == WR * WC, "one 32-row segment per wave");
-  constexpr int LD = LdsLayout<PREC>::LD;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+// One LDS stage: the J tile [TM][LD] and the S tile [TN][LD] (FP32), or hi and
+// lo copies of each (bf16), starting at byte offset `base` of the shared memory.
+template <int PREC, int TM, int TN>
+struct Stage {
+  float *Jf, *Sf;
+  u16 *Jh, *Jl, *Sh, *Sl;
+  __device__ Stage(unsigned char *base) {
+    constexpr int LD = LdsLayout<PREC>::LD;
+    Jf = (float *)base;
+    Sf = Jf + TM * LD;
+    Jh = (u16 *)base;
+    Jl = Jh + TM * LD;
+    Sh = Jl + TM * LD;
+    Sl = Sh + TN * LD;
+  }
+};
 
-  // Work item: XCD x = L % 8 takes the rows of rank x, x + 8, ... (rank 0 =
-  // largest k, the most work); within a row the l tiles of one column tile
-  // follow each other (they read the same S columns, kept in that XCD's L2).
+// A workgroup's tile: XCD x = L % 8 takes the rows of rank x, x + 8, ...
+// (rank 0 = largest k, the most work); within a row the l tiles of one column
+// tile follow each other (they read the same S columns, kept in that XCD's L2).
+struct Tile {
+  int ki, tm, ncol, c0, lb0, lb_last, tile_lo, top_cap;
+  int64_t r, sbase, dbase;
+};
+
+template <int TM, int TN>
+__device__ inline bool tile_of_block(const FusedArgs &a, int tiles_m, int tiles_n, int kcount,
+                                     Tile &t) {
   const int64_t per_row = (int64_t)tiles_m * tiles_n;
   const int64_t L = blockIdx.x;
   const int64_t q = L >> 3;
   const int64_t kr = (L & 7) + 8 * (q / per_row);
-  if (kr >= kcount) return;
-  const int tm = (int)(q % per_row % tiles_m);
+  if (kr >= kcount) return false;
+  t.tm = (int)(q % per_row % tiles_m);
   const int tn = (int)(q % per_row / tiles_m);
-  const int ki = kcount - 1 - (int)kr;
-  const int64_t r = a.k0 + ki;
+  t.ki = kcount - 1 - (int)kr;
+  t.r = a.k0 + t.ki;
+  t.ncol = a.col_cnt ? a.col_cnt[t.r] : a.ncol;
+  t.c0 = tn * TN;
+  if (t.c0 >= t.ncol) return false;
+  t.lb0 = t.tm * (TM / 16);
+  t.lb_last = a.nlb - 1;
+  if (a.col_lmax) t.lb_last = min(t.lb_last, (a.col_lmax[a.col_off[t.r] + t.c0] - a.lmin) >> 4);
+  if (t.lb0 > t.lb_last) return false;
+  t.tile_lo = 16 * t.lb0;                        // first row of the tile (l - lmin)
+  t.top_cap = 16 * t.lb_last + 15 - t.tile_lo;   // last tile row any column needs
+  t.sbase = a.col_off ? a.col_off[t.r] * a.s_cstride : t.r * a.s_kstride;
+  t.dbase = a.col_off ? (a.col_off[t.r] - a.col_base) * (int64_t)a.nl
+                      : t.r * (int64_t)a.nl * t.ncol;
+  return true;
+}
 
-  const int ncol = a.col_cnt ? a.col_cnt[r] : a.ncol;
-  const int c0 = tn * TN;
-  if (c0 >= ncol) return;
-  const int lb0 = tm * (TM / 16);
-  int lb_last = a.nlb - 1;
-  if (a.col_lmax) lb_last = min(lb_last, (a.col_lmax[a.col_off[r] + c0] - a.lmin) >> 4);
-  if (lb0 > lb_last) return;  // uniform
-  const int tile_lo = 16 * lb0;                  // first row of the tile (l - lmin)
-  const int top_cap = 16 * lb_last + 15 - tile_lo;  // last tile row any column needs
+// Active chunks: those whose largest top row reaches the tile's first row, as
+// a 128-bit mask (the same in every wave), and the lane's entries of the
+// chunk table (chunk_top reads them back).
+struct Chunks {
+  int cm0, cm1;
+  uint64_t act0, act1;
+};
 
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int g = lane >> 4, r16 = lane & 15;
-  const int wr = w % WR, wc = w / WR;
-
-  const int64_t sbase = a.col_off ? a.col_off[r] * a.s_cstride : r * a.s_kstride;
-  const int64_t dbase = a.col_off ? (a.col_off[r] - a.col_base) * (int64_t)a.nl
-                                  : r * (int64_t)a.nl * ncol;
-
-  // LDS: J tile [TM][LD], S tile [TN][LD] (FP32), or hi and lo copies of each (bf16)
-  float *Jf = (float *)smem;
-  float *Sf = Jf + TM * LD;
-  u16 *Jh = (u16 *)smem, *Jl = Jh + TM * LD;
-  u16 *Sh = Jl + TM * LD, *Sl = Sh + TN * LD;
-
-  // generation role: wave w regenerates segment sg (rows 32 w .. 32 w + 31 of the tile)
-  const int sg = tm * NSEG + w;
-  const bool seg_ok = sg < a.nseg;
-  const int seg_hi = 32 * sg + 31;  // l - lmin of the segment's top row
-  const int64_t rowb = (int64_t)ki * a.ntp;
-  const double2 *seedp = a.seed + ((int64_t)ki * a.nseg + (seg_ok ? sg : 0)) * a.ntp;
-
-  // S staging role: NT threads cover TN columns x 64 nodes in 16-byte pieces
-  constexpr int SP = TN * KB / 4;           // float4 pieces per chunk
-  constexpr int SPT = (SP + NT - 1) / NT;   // per thread (the last round may be partial)
-  const bool s_vec = (a.s_cstride % 4 == 0) && (sbase % 4 == 0) && (a.ntau % 4 == 0);
-
-  f4 acc[MBW][NBW];
-#pragma unroll
-  for (int i = 0; i < MBW; ++i)
-#pragma unroll
-    for (int j = 0; j < NBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-  // Column blocks whose models stop below a row block skip its products: the
-  // last 16-row block (relative to the tile) that column block j of this wave
-  // needs, from the l_max of its first column (columns are ordered by l_max,
-  // largest first, within a row).
-  int jlast[NBW];
-#pragma unroll
-  for (int j = 0; j < NBW; ++j) {
-    const int cj = c0 + wc * NBW * 16 + 16 * j;
-    jlast[j] = (a.col_lmax && cj < ncol) ? ((a.col_lmax[a.col_off[r] + cj] - a.lmin) >> 4) - lb0
-                                         : (cj < ncol ? a.nlb - 1 - lb0 : -1);
-  }
-
-  // Active chunks: those whose largest top row reaches the tile's first row.
+__device__ inline Chunks active_chunks(const FusedArgs &a, const Tile &t, int lane) {
   const int nch = (int)(a.ntp / KB);  // <= 128
-  const int *cmr = a.cmax + (int64_t)ki * nch;
-  const int thr = a.lmin + tile_lo;
-  const int cm0 = lane < nch ? cmr[lane] : -1;
-  const int cm1 = lane + 64 < nch ? cmr[lane + 64] : -1;
-  const uint64_t act0 = __ballot(cm0 >= thr), act1 = __ballot(cm1 >= thr);
+  const int *cmr = a.cmax + (int64_t)t.ki * nch;
+  const int thr = a.lmin + t.tile_lo;
+  Chunks ch;
+  ch.cm0 = lane < nch ? cmr[lane] : -1;
+  ch.cm1 = lane + 64 < nch ? cmr[lane + 64] : -1;
+  ch.act0 = __ballot(ch.cm0 >= thr);
+  ch.act1 = __ballot(ch.cm1 >= thr);
+  return ch;
+}
 
-  // Per-chunk inputs, loaded one active chunk ahead: R, seed pair and 1/x of
-  // this lane's node, and this thread's pieces of the S tile.
-  int Rn = -1;
+// The last tile row that holds data in chunk c (its largest R, capped).
+__device__ inline int chunk_top(const FusedArgs &a, const Tile &t, const Chunks &ch, int c) {
+  const int cmax = __shfl(c < 64 ? ch.cm0 : ch.cm1, c & 63, 64);
+  return min(cmax - a.lmin - t.tile_lo, t.top_cap);
+}
+
+// The S tile [TN columns][KB nodes] moves in 16-byte pieces, NTH threads.
+template <int TN, int NTH>
+struct SPieces {
+  static constexpr int SP = TN * KB / 4;
+  static constexpr int SPT = (SP + NTH - 1) / NTH;  // per thread (the last round may be partial)
+};
+
+// One chunk's inputs as one producing thread holds them: R, seed pair and 1/x
+// of the lane's node (for the wave's segment) and the thread's S pieces.
+template <int SPT>
+struct ChunkIn {
+  int R = -1;
   double2 sd = make_double2(0.0, 0.0);
   double nx = 0.0;
   float4 sv[SPT];
-  auto load_chunk = [&](int c) {
-    const int n = c * KB + lane;
-    Rn = a.rtop[rowb + n];
-    nx = a.nix[rowb + n];
-    if (seg_ok) sd = seedp[n];  // read whatever the node's R; used only below R
-#pragma unroll
-    for (int p = 0; p < SPT; ++p) {
-      if (SP % NT != 0 && p * NT + tid >= SP) break;
-      const int e = (p * NT + tid) * 4;  // element within [TN][KB]
-      const int col = e / KB, nn = e % KB;
-      const int cg = c0 + col, ng = c * KB + nn;
-      const float *src = a.S + sbase + (int64_t)(cg < ncol ? cg : 0) * a.s_cstride + ng;
-      if (cg < ncol && s_vec && ng + 4 <= a.ntau) {
-        sv[p] = *(const float4 *)src;
-      } else {
-        float t4[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) t4[u] = (cg < ncol && ng + u < a.ntau) ? src[u] : 0.f;
-        sv[p] = make_float4(t4[0], t4[1], t4[2], t4[3]);
-      }
-    }
-  };
+};
 
-  int c = next_chunk(act0, act1, 0);
-  if (c >= 0) load_chunk(c);
-  while (c >= 0) {
-    const int cmax = __shfl(c < 64 ? cm0 : cm1, c & 63, 64);  // the chunk's largest R
-    const int top_tr = min(cmax - a.lmin - tile_lo, top_cap);
+// What a producing wave needs to regenerate its segment and stage S.
+struct Producer {
+  int seg_hi;         // l - lmin of the segment's top row
+  bool seg_ok;        // the segment exists (sg < nseg)
+  bool s_vec;         // S columns are 16-byte aligned
+  int64_t rowb;       // chunk row offset in the per-node tables
+  const double2 *seedp;
+};
 
-    // regenerate this wave's segment for the 64 nodes (zeros above each node's R)
-    if (seg_ok && 32 * w <= top_tr) {
-      const int Rrel = Rn - a.lmin;                  // < 0 when the node has no row
-      const bool liveA = Rn >= 0 && Rrel >= seg_hi;  // live through the upper 16 rows
-      const bool liveB = Rn >= 0 && Rrel >= seg_hi - 16;
-      double cur = liveB ? sd.x : 0.0, nxt = liveB ? sd.y : 0.0, ix = liveB ? nx : 0.0;
-      const double d2 = ix + ix;
+__device__ inline Producer producer_of(const FusedArgs &a, const Tile &t, int sg) {
+  Producer p;
+  p.seg_ok = sg < a.nseg;
+  p.seg_hi = 32 * sg + 31;
+  p.rowb = (int64_t)t.ki * a.ntp;
+  p.seedp = a.seed + ((int64_t)t.ki * a.nseg + (p.seg_ok ? sg : 0)) * a.ntp;
+  p.s_vec = (a.s_cstride % 4 == 0) && (t.sbase % 4 == 0) && (a.ntau % 4 == 0);
+  return p;
+}
+
+template <int TN, int NTH>
+__device__ inline void load_chunk_in(const FusedArgs &a, const Tile &t, const Producer &p, int c,
+                                     int lane, int pt, ChunkIn<SPieces<TN, NTH>::SPT> &in) {
+  constexpr int SP = SPieces<TN, NTH>::SP, SPT = SPieces<TN, NTH>::SPT;
+  const int n = c * KB + lane;
+  in.R = a.rtop[p.rowb + n];
+  in.nx = a.nix[p.rowb + n];
+  if (p.seg_ok) in.sd = p.seedp[n];  // read whatever the node's R; used only below R
 #pragma unroll
-      for (int half = 1; half >= 0; --half) {
-        const bool live = half ? liveA : liveB;
-        const int hi_row = seg_hi - 16 * (1 - half);  // l - lmin of the block's top row
-        const int tr0 = 32 * w + 16 * half;          // tile row of the block's bottom row
-        double t = 0.0;
+  for (int q = 0; q < SPT; ++q) {
+    if (SP % NTH != 0 && q * NTH + pt >= SP) break;
+    const int e = (q * NTH + pt) * 4;  // element within [TN][KB]
+    const int col = e / KB, nn = e % KB;
+    const int cg = t.c0 + col, ng = c * KB + nn;
+    const float *src = a.S + t.sbase + (int64_t)(cg < t.ncol ? cg : 0) * a.s_cstride + ng;
+    if (cg < t.ncol && p.s_vec && ng + 4 <= a.ntau) {
+      in.sv[q] = *(const float4 *)src;
+    } else {
+      float t4[4];
 #pragma unroll
-        for (int rr = 15; rr >= 0; --rr) {
-          float v = 0.f;
-          if (live) {
-            if (rr == 15 || rr == 7) t = (double)(2 * (a.lmin + hi_row - 15 + rr) + 1) * ix;
-            v = (float)cur;
-            const double pv = rec_step(t, cur, nxt);
-            nxt = cur;
-            cur = pv;
-            t -= d2;
-          }
-          const int row = tr0 + rr;
-          if (PREC == 1) {
-            Jf[row * LD + lane] = v;
-          } else {
-            const __bf16 h = (__bf16)v;
-            Jh[row * LD + lane] = bf16_bits(h);
-            Jl[row * LD + lane] = bf16_bits((__bf16)(v - (float)h));
-          }
-        }
-      }
+      for (int u = 0; u < 4; ++u) t4[u] = (cg < t.ncol && ng + u < a.ntau) ? src[u] : 0.f;
+      in.sv[q] = make_float4(t4[0], t4[1], t4[2], t4[3]);
     }
-    // S registers -> LDS
+  }
+}
+
+// Regenerate the 32 rows of a segment (tile rows tr_base .. tr_base + 31) for
+// the lane's node, zeros above its R.
+template <int PREC, int TM, int TN, int SPT>
+__device__ inline void gen_segment(const FusedArgs &a, const Producer &p, const ChunkIn<SPT> &in,
+                                   int tr_base, int lane, const Stage<PREC, TM, TN> &sm) {
+  constexpr int LD = LdsLayout<PREC>::LD;
+  const int Rrel = in.R - a.lmin;                       // < 0 when the node has no row
+  const bool liveA = in.R >= 0 && Rrel >= p.seg_hi;       // live through the upper 16 rows
+  const bool liveB = in.R >= 0 && Rrel >= p.seg_hi - 16;
+  double cur = liveB ? in.sd.x : 0.0, nxt = liveB ? in.sd.y : 0.0, ix = liveB ? in.nx : 0.0;
+  const double d2 = ix + ix;
 #pragma unroll
-    for (int p = 0; p < SPT; ++p) {
-      if (SP % NT != 0 && p * NT + tid >= SP) break;
-      const int e = (p * NT + tid) * 4;
-      const int col = e / KB, nn = e % KB;
-      const float v4[4] = {sv[p].x, sv[p].y, sv[p].z, sv[p].w};
+  for (int half = 1; half >= 0; --half) {
+    const bool live = half ? liveA : liveB;
+    const int hi_row = p.seg_hi - 16 * (1 - half);  // l - lmin of the block's top row
+    const int tr0 = tr_base + 16 * half;            // tile row of the block's bottom row
+    double tt = 0.0;
+#pragma unroll
+    for (int rr = 15; rr >= 0; --rr) {
+      float v = 0.f;
+      if (live) {
+        if (rr == 15 || rr == 7) tt = (double)(2 * (a.lmin + hi_row - 15 + rr) + 1) * ix;
+        v = (float)cur;
+        const double pv = rec_step(tt, cur, nxt);
+        nxt = cur;
+        cur = pv;
+        tt -= d2;
+      }
+      const int row = tr0 + rr;
       if (PREC == 1) {
-        *(float4 *)(Sf + col * LD + nn) = sv[p];
+        sm.Jf[row * LD + lane] = v;
       } else {
-        u16 hh[4], ll[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const __bf16 h = (__bf16)v4[u];
-          hh[u] = bf16_bits(h);
-          ll[u] = bf16_bits((__bf16)(v4[u] - (float)h));
-        }
-        *(uint2 *)(Sh + col * LD + nn) = make_uint2(hh[0] | ((unsigned)hh[1] << 16),
-                                                   hh[2] | ((unsigned)hh[3] << 16));
-        *(uint2 *)(Sl + col * LD + nn) = make_uint2(ll[0] | ((unsigned)ll[1] << 16),
-                                                   ll[2] | ((unsigned)ll[3] << 16));
+        const __bf16 h = (__bf16)v;
+        sm.Jh[row * LD + lane] = bf16_bits(h);
+        sm.Jl[row * LD + lane] = bf16_bits((__bf16)(v - (float)h));
       }
     }
-    __syncthreads();
-    // the next active chunk's inputs are in flight while the matrix cores run
-    const int cn = next_chunk(act0, act1, c + 1);
-    if (cn >= 0) load_chunk(cn);
+  }
+}
 
-    // this wave's rows: blocks wr*MBW .. +MBW-1 of the tile; those <= top_tr hold data
-    const int nb = min(MBW, (top_tr - wr * MBW * 16) / 16 + 1);
-    if (top_tr >= wr * MBW * 16 && nb > 0) {
+// The thread's S pieces into the stage (FP32, or split into bf16 hi and lo).
+template <int PREC, int TM, int TN, int NTH>
+__device__ inline void store_s(const ChunkIn<SPieces<TN, NTH>::SPT> &in, int pt,
+                               const Stage<PREC, TM, TN> &sm) {
+  constexpr int LD = LdsLayout<PREC>::LD;
+  constexpr int SP = SPieces<TN, NTH>::SP, SPT = SPieces<TN, NTH>::SPT;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {  // two 32-node blocks, in increasing order
-        const int kofs = 32 * h + 8 * g;
-        if (PREC == 1) {
-          float bfv[NBW][8];
+  for (int q = 0; q < SPT; ++q) {
+    if (SP % NTH != 0 && q * NTH + pt >= SP) break;
+    const int e = (q * NTH + pt) * 4;
+    const int col = e / KB, nn = e % KB;
+    if (PREC == 1) {
+      *(float4 *)(sm.Sf + col * LD + nn) = in.sv[q];
+    } else {
+      const float v4[4] = {in.sv[q].x, in.sv[q].y, in.sv[q].z, in.sv[q].w};
+      u16 hh[4], ll[4];
 #pragma unroll
-          for (int j = 0; j < NBW; ++j) {
-            const float *src = Sf + (wc * NBW * 16 + 16 * j + r16) * LD + kofs;
-            const float4 u = *(const float4 *)src, v = *(const float4 *)(src + 4);
-            bfv[j][0] = u.x; bfv[j][1] = u.y; bfv[j][2] = u.z; bfv[j][3] = u.w;
-            bfv[j][4] = v.x; bfv[j][5] = v.y; bfv[j][6] = v.z; bfv[j][7] = v.w;
-          }
+      for (int u = 0; u < 4; ++u) {
+        const __bf16 h = (__bf16)v4[u];
+        hh[u] = bf16_bits(h);
+        ll[u] = bf16_bits((__bf16)(v4[u] - (float)h));
+      }
+      *(uint2 *)(sm.Sh + col * LD + nn) = make_uint2(hh[0] | ((unsigned)hh[1] << 16),
+                                                     hh[2] | ((unsigned)hh[3] << 16));
+      *(uint2 *)(sm.Sl + col * LD + nn) = make_uint2(ll[0] | ((unsigned)ll[1] << 16),
+                                                     ll[2] | ((unsigned)ll[3] << 16));
+    }
+  }
+}
+
+// Column blocks whose models stop below a row block skip its products: the
+// last 16-row block (relative to the tile) that column block j of the wave
+// needs, from the l_max of its first column (columns are ordered by l_max,
+// largest first, within a row).
+template <int NBW>
+__device__ inline void column_limits(const FusedArgs &a, const Tile &t, int wc, int (&jlast)[NBW]) {
 #pragma unroll
-          for (int i = 0; i < MBW; ++i) {
-            if (i < nb) {
-              const float *src = Jf + (wr * MBW * 16 + 16 * i + r16) * LD + kofs;
-              const float4 u = *(const float4 *)src, v = *(const float4 *)(src + 4);
-              const float af[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
-              if (wr * MBW + i <= jlast[NBW - 1]) {  // every column block: accumulators in turn
+  for (int j = 0; j < NBW; ++j) {
+    const int cj = t.c0 + wc * NBW * 16 + 16 * j;
+    jlast[j] = (a.col_lmax && cj < t.ncol)
+                   ? ((a.col_lmax[a.col_off[t.r] + cj] - a.lmin) >> 4) - t.lb0
+                   : (cj < t.ncol ? a.nlb - 1 - t.lb0 : -1);
+  }
+}
+
+// One chunk's products for one multiplying wave: its row blocks are
+// bi = bofs + BSTR * i of the tile (those with data: 16 bi <= top_tr), its
+// column blocks wc * NBW + j; the two 32-node blocks of the chunk in
+// increasing order.  Every accumulator sees its terms in the same order
+// whichever wave owns it.
+template <int PREC, int TM, int TN, int MBW, int NBW, int BSTR>
+__device__ inline void mfma_chunk(f4 (&acc)[MBW][NBW], const int (&jlast)[NBW], int bofs, int wc,
+                                  int top_tr, int g, int r16, const Stage<PREC, TM, TN> &sm) {
+  constexpr int LD = LdsLayout<PREC>::LD;
+  if (16 * bofs > top_tr) return;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int kofs = 32 * h + 8 * g;
+    if (PREC == 1) {
+      float bfv[NBW][8];
+#pragma unroll
+      for (int j = 0; j < NBW; ++j) {
+        const float *src = sm.Sf + (wc * NBW * 16 + 16 * j + r16) * LD + kofs;
+        const float4 u = *(const float4 *)src, v = *(const float4 *)(src + 4);
+        bfv[j][0] = u.x; bfv[j][1] = u.y; bfv[j][2] = u.z; bfv[j][3] = u.w;
+        bfv[j][4] = v.x; bfv[j][5] = v.y; bfv[j][6] = v.z; bfv[j][7] = v.w;
+      }
+#pragma unroll
+      for (int i = 0; i < MBW; ++i) {
+        const int bi = bofs + BSTR * i;
+        if (16 * bi <= top_tr) {
+          const float *src = sm.Jf + (16 * bi + r16) * LD + kofs;
+          const float4 u = *(const float4 *)src, v = *(const float4 *)(src + 4);
+          const float af[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+          if (bi <= jlast[NBW - 1]) {  // every column block: accumulators in turn
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+#pragma unroll
+              for (int j = 0; j < NBW; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e], acc[i][j], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int j = 0; j < NBW; ++j)
+              if (bi <= jlast[j]) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-#pragma unroll
-                  for (int j = 0; j < NBW; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e], acc[i][j],
-                                                                     0, 0, 0);
-              } else {
-#pragma unroll
-                for (int j = 0; j < NBW; ++j)
-                  if (wr * MBW + i <= jlast[j]) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e],
-                                                                       acc[i][j], 0, 0, 0);
-                  }
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[e], bfv[j][e], acc[i][j],
+                                                                   0, 0, 0);
               }
-            }
-          }
-        } else {
-          bf8 bh[NBW], bl[NBW];
-#pragma unroll
-          for (int j = 0; j < NBW; ++j) {
-            const int row = wc * NBW * 16 + 16 * j + r16;
-            bh[j] = *(const bf8 *)(Sh + row * LD + kofs);
-            bl[j] = *(const bf8 *)(Sl + row * LD + kofs);
-          }
-#pragma unroll
-          for (int i = 0; i < MBW; ++i) {
-            if (i < nb) {
-              const int row = wr * MBW * 16 + 16 * i + r16;
-              const bf8 ah = *(const bf8 *)(Jh + row * LD + kofs);
-              const bf8 al = *(const bf8 *)(Jl + row * LD + kofs);
-              if (wr * MBW + i <= jlast[NBW - 1]) {  // every column block: accumulators in turn
-#pragma unroll
-                for (int j = 0; j < NBW; ++j)
-                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < NBW; ++j)
-                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < NBW; ++j)
-                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-              } else {
-#pragma unroll
-                for (int j = 0; j < NBW; ++j)
-                  if (wr * MBW + i <= jlast[j]) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-                  }
-              }
-            }
           }
         }
       }
-    }
-    __syncthreads();
-    c = cn;
-  }
-
-  // output: lane holds rows 4g + v of each 16-row block, column r16 of each column block
+    } else {
+      bf8 bh[NBW], bl[NBW];
 #pragma unroll
-  for (int i = 0; i < MBW; ++i) {
-    const int blk = lb0 + wr * MBW + i;
-    if (blk > lb_last) break;
+      for (int j = 0; j < NBW; ++j) {
+        const int row = wc * NBW * 16 + 16 * j + r16;
+        bh[j] = *(const bf8 *)(sm.Sh + row * LD + kofs);
+        bl[j] = *(const bf8 *)(sm.Sl + row * LD + kofs);
+      }
 #pragma unroll
-    for (int j = 0; j < NBW; ++j) {
-      const int cc = c0 + wc * NBW * 16 + 16 * j + r16;
-      if (cc >= ncol) continue;
+      for (int i = 0; i < MBW; ++i) {
+        const int bi = bofs + BSTR * i;
+        if (16 * bi <= top_tr) {
+          const int row = 16 * bi + r16;
+          const bf8 ah = *(const bf8 *)(sm.Jh + row * LD + kofs);
+          const bf8 al = *(const bf8 *)(sm.Jl + row * LD + kofs);
+          if (bi <= jlast[NBW - 1]) {  // every column block: accumulators in turn
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = blk * 16 + 4 * g + v;
-        if (row < a.nl) {
-          const int64_t o = a.dtrans ? (int64_t)cc * a.nl + row : (int64_t)row * ncol + cc;
-          a.delta[dbase + o] = acc[i][j][v];
+            for (int j = 0; j < NBW; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NBW; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NBW; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int j = 0; j < NBW; ++j)
+              if (bi <= jlast[j]) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+              }
+          }
         }
       }
     }
   }
 }
 
+// Accumulators to Delta: lane holds rows 4g + v of each 16-row block, column
+// r16 of each column block.
+template <int MBW, int NBW, int BSTR>
+__device__ inline void store_acc(const FusedArgs &a, const Tile &t, const f4 (&acc)[MBW][NBW],
+                                 int bofs, int wc, int g, int r16) {
+#pragma unroll
+  for (int i = 0; i < MBW; ++i) {
+    const int blk = t.lb0 + bofs + BSTR * i;
+    if (blk > t.lb_last) break;
+#pragma unroll
+    for (int j = 0; j < NBW; ++j) {
+      const int cc = t.c0 + wc * NBW * 16 + 16 * j + r16;
+      if (cc >= t.ncol) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = blk * 16 + 4 * g + v;
+        if (row < a.nl) {
+          const int64_t o = a.dtrans ? (int64_t)cc * a.nl + row : (int64_t)row * t.ncol + cc;
+          a.delta[t.dbase + o] = acc[i][j][v];
+        }
+      }
+    }
+  }
+}
+
+// One workgroup per (k row, TM-row l tile, TN-column tile), WR x WC waves that
+// all take every role in turn: per active chunk each wave regenerates one
+// 32-row segment, the threads stage S, and after a barrier each wave
+// multiplies its row blocks wr, wr + WR, ... (interleaved, so that the waves
+// share a tile's partly filled upper blocks) by its column blocks; the next
+// chunk's inputs load meanwhile.
 template <int PREC, int WR, int WC, int MBW, int NBW>
-hipError_t launch_fused_t(const FusedArgs &a, int kcount, int max_ncol, hipStream_t s) {
+__global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, int tiles_m,
+                                                                  int tiles_n, int kcount) {
+  constexpr int NT = 64 * WR * WC;
   constexpr int TM = WR * MBW * 16, TN = WC * NBW * 16;
-  const int tiles_m = (a.nlb * 16 + TM - 1) / TM;
-  const int tiles_n = (max_ncol + TN - 1) / TN;
-  const int64_t grid = 8 * (((int64_t)kcount + 7) / 8) * tiles_m * tiles_n;
-  if (grid > 0x7fffffff || grid < 1) return hipErrorInvalidValue;
-  const size_t lds = LdsLayout<PREC>::bytes(TM, TN);
-  auto kern = fused_gemm_kernel<PREC, WR, WC, MBW, NBW>;
-  // the large-LDS limit is a per-device function attribute
-  static bool attr_set[64] = {};
+  static_assert(TM / 32 == WR * WC, "one 32-row segment per wave");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  Tile t;
+  if (!tile_of_block<TM, TN>(a, tiles_m, tiles_n, kcount, t)) return;  // uniform
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int wr = w % WR, wc = w / WR;
+  const Stage<PREC, TM, TN> sm(smem);
+  const Producer p = producer_of(a, t, t.tm * (TM / 32) + w);
+  const Chunks ch = active_chunks(a, t, lane);
+
+  f4 acc[MBW][NBW];
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  int jlast[NBW];
+  column_limits(a, t, wc, jlast);
+
+  ChunkIn<SPieces<TN, NT>::SPT> in;
+  int c = next_chunk(ch.act0, ch.act1, 0);
+  if (c >= 0) load_chunk_in<TN, NT>(a, t, p, c, lane, tid, in);
+  while (c >= 0) {
+    const int top_tr = chunk_top(a, t, ch, c);
+    if (p.seg_ok && 32 * w <= top_tr) gen_segment(a, p, in, 32 * w, lane, sm);
+    store_s<PREC, TM, TN, NT>(in, tid, sm);
+    __syncthreads();
+    // the next active chunk's inputs are in flight while the matrix cores run
+    const int cn = next_chunk(ch.act0, ch.act1, c + 1);
+    if (cn >= 0) load_chunk_in<TN, NT>(a, t, p, cn, lane, tid, in);
+    mfma_chunk<PREC, TM, TN, MBW, NBW, WR>(acc, jlast, wr, wc, top_tr, g, r16, sm);
+    __syncthreads();
+    c = cn;
+  }
+  store_acc<MBW, NBW, WR>(a, t, acc, wr, wc, g, r16);
+}
+
+// Warp-specialised form with two LDS stages: 8 waves, of which waves 0..3
+// (2 x 2) only multiply and waves 4..7 only produce.  While the multiplying
+// waves work on chunk c from one stage, the producing waves regenerate the
+// J segments of the next active chunk (one 32-row segment per wave) and stage
+// its S columns into the other stage, then issue the loads of the chunk after
+// it; one barrier per chunk.  Each SIMD runs one wave of each kind, so the
+// FP64 recurrence, the S traffic and the barrier waits overlap the matrix
+// cores.  The products and their order are those of fused_gemm_kernel with
+// WR = WC = 2.
+template <int PREC, int MBW, int NBW>
+__global__ __launch_bounds__(512) void fused_ws_kernel(FusedArgs a, int tiles_m, int tiles_n,
+                                                       int kcount) {
+  constexpr int WR = 2, NP = 256;  // multiplying waves 2 x 2; producing threads
+  constexpr int TM = WR * MBW * 16, TN = 2 * NBW * 16;
+  static_assert(TM / 32 == 4, "one 32-row segment per producing wave");
+  constexpr size_t STAGE = LdsLayout<PREC>::bytes(TM, TN);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  Tile t;
+  if (!tile_of_block<TM, TN>(a, tiles_m, tiles_n, kcount, t)) return;  // uniform
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const Chunks ch = active_chunks(a, t, lane);
+  int c = next_chunk(ch.act0, ch.act1, 0);
+
+  if (w >= 4) {
+    // producing waves: chunk cn into stage st, then the loads of the next one
+    const int pw = w - 4, pt = tid - 4 * 64;
+    const Producer p = producer_of(a, t, t.tm * 4 + pw);
+    ChunkIn<SPieces<TN, NP>::SPT> in;
+    auto produce = [&](int cp, int st) {
+      const Stage<PREC, TM, TN> sm(smem + st * STAGE);
+      const int top_tr = chunk_top(a, t, ch, cp);
+      if (p.seg_ok && 32 * pw <= top_tr) gen_segment(a, p, in, 32 * pw, lane, sm);
+      store_s<PREC, TM, TN, NP>(in, pt, sm);
+      const int cq = next_chunk(ch.act0, ch.act1, cp + 1);
+      if (cq >= 0) load_chunk_in<TN, NP>(a, t, p, cq, lane, pt, in);
+    };
+    if (c >= 0) {
+      load_chunk_in<TN, NP>(a, t, p, c, lane, pt, in);
+      produce(c, 0);
+    }
+    __syncthreads();
+    int st = 0;
+    while (c >= 0) {
+      const int cn = next_chunk(ch.act0, ch.act1, c + 1);
+      if (cn >= 0) produce(cn, st ^ 1);
+      __syncthreads();
+      st ^= 1;
+      c = cn;
+    }
+    return;
+  }
+
+  // multiplying waves
+  const int g = lane >> 4, r16 = lane & 15;
+  const int wr = w % WR, wc = w / WR;
+  f4 acc[MBW][NBW];
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int j = 0; j < NBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  int jlast[NBW];
+  column_limits(a, t, wc, jlast);
+  __syncthreads();  // the first chunk is staged
+  int st = 0;
+  while (c >= 0) {
+    const Stage<PREC, TM, TN> sm(smem + st * STAGE);
+    mfma_chunk<PREC, TM, TN, MBW, NBW, WR>(acc, jlast, wr, wc, chunk_top(a, t, ch, c), g, r16, sm);
+    __syncthreads();
+    st ^= 1;
+    c = next_chunk(ch.act0, ch.act1, c + 1);
+  }
+  store_acc<MBW, NBW, WR>(a, t, acc, wr, wc, g, r16);
+}
+
+// Sets the large-LDS limit of a kernel once per device (a per-device function
+// attribute).
+template <typename K>
+hipError_t allow_lds(K kern, size_t lds, bool (&done)[64]) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  if (lds > 64 * 1024 && !attr_set[dev]) {
+  if (lds > 64 * 1024 && !done[dev]) {
     e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
     if (e != hipSuccess) return e;
-    attr_set[dev] = true;
+    done[dev] = true;
   }
+  return hipSuccess;
+}
+
+int64_t fused_grid(const FusedArgs &a, int kcount, int max_ncol, int tm, int tn, int &tiles_m,
+                   int &tiles_n) {
+  tiles_m = (a.nlb * 16 + tm - 1) / tm;
+  tiles_n = (max_ncol + tn - 1) / tn;
+  return 8 * (((int64_t)kcount + 7) / 8) * tiles_m * tiles_n;
+}
+
+template <int PREC, int WR, int WC, int MBW, int NBW>
+hipError_t launch_fused_t(const FusedArgs &a, int kcount, int max_ncol, hipStream_t s) {
+  constexpr int TM = WR * MBW * 16, TN = WC * NBW * 16;
+  int tiles_m, tiles_n;
+  const int64_t grid = fused_grid(a, kcount, max_ncol, TM, TN, tiles_m, tiles_n);
+  if (grid > 0x7fffffff || grid < 1) return hipErrorInvalidValue;
+  const size_t lds = LdsLayout<PREC>::bytes(TM, TN);
+  auto kern = fused_gemm_kernel<PREC, WR, WC, MBW, NBW>;
+  static bool done[64] = {};
+  hipError_t e = allow_lds(kern, lds, done);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * WR * WC), lds, s, a, tiles_m,
                      tiles_n, kcount);
+  return hipGetLastError();
+}
+
+template <int PREC, int MBW, int NBW>
+hipError_t launch_ws_t(const FusedArgs &a, int kcount, int max_ncol, hipStream_t s) {
+  constexpr int TM = 2 * MBW * 16, TN = 2 * NBW * 16;
+  int tiles_m, tiles_n;
+  const int64_t grid = fused_grid(a, kcount, max_ncol, TM, TN, tiles_m, tiles_n);
+  if (grid > 0x7fffffff || grid < 1) return hipErrorInvalidValue;
+  const size_t lds = 2 * LdsLayout<PREC>::bytes(TM, TN);
+  auto kern = fused_ws_kernel<PREC, MBW, NBW>;
+  static bool done[64] = {};
+  hipError_t e = allow_lds(kern, lds, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(512), lds, s, a, tiles_m, tiles_n, kcount);
   return hipGetLastError();
 }
 
@@ -450,6 +654,7 @@ hipError_t launch_fused_p(const FusedArgs &a, int shape, int kcount, int max_nco
     case 3: return launch_fused_t<PREC, 2, 4, 8, 4>(a, kcount, max_ncol, s);  // 256 x 256
     case 4: return launch_fused_t<PREC, 8, 1, 2, 1>(a, kcount, max_ncol, s);  // 256 x 16
     case 5: return launch_fused_t<PREC, 4, 1, 2, 1>(a, kcount, max_ncol, s);  // 128 x 16
+    case 6: return launch_ws_t<PREC, 4, 4>(a, kcount, max_ncol, s);           // 128 x 128, 2 stages
     default: return hipErrorInvalidValue;
   }
 }
@@ -458,7 +663,7 @@ hipError_t launch_fused_p(const FusedArgs &a, int shape, int kcount, int max_nco
 
 FusedShape fused_shape_at(int i) {
   static const FusedShape shapes[kFusedShapeCount] = {
-      {256, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 16}, {128, 16}};
+      {256, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 16}, {128, 16}, {128, 128}};
   return shapes[i];
 }
 
