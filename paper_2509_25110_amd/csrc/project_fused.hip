@@ -128,6 +128,15 @@ struct LdsLayout<2> {  // bf16 hi and lo rows of KB + 8 (144 bytes: 16 rows hit 
 
 __device__ inline u16 bf16_bits(__bf16 v) { return __builtin_bit_cast(u16, v); }
 
+// x rounded to FP32, as a value the compiler may not look through: the bf16
+// split that follows must round this FP32 value (as the table pipeline does),
+// not x itself (a direct FP64 -> bf16 rounding differs in rare ties).
+__device__ inline float f32_opaque(double x) {
+  float v = (float)x;
+  asm("" : "+v"(v));
+  return v;
+}
+
 // One LDS stage: the J tile [TM][LD] and the S tile [TN][LD] (FP32), or hi and
 // lo copies of each (bf16), starting at byte offset `base` of the shared memory.
 template <int PREC, int TM, int TN>
@@ -203,7 +212,7 @@ __device__ inline Chunks active_chunks(const FusedArgs &a, const Tile &t, int la
 // The last tile row that holds data in chunk c (its largest R, capped).
 __device__ inline int chunk_top(const FusedArgs &a, const Tile &t, const Chunks &ch, int c) {
   const int cmax = __shfl(c < 64 ? ch.cm0 : ch.cm1, c & 63, 64);
-  return min(cmax - a.lmin - t.tile_lo, t.top_cap);
+  return __builtin_amdgcn_readfirstlane(min(cmax - a.lmin - t.tile_lo, t.top_cap));  // uniform
 }
 
 // The S tile [TN columns][KB nodes] moves in 16-byte pieces, NTH threads.
@@ -269,33 +278,36 @@ __device__ inline void load_chunk_in(const FusedArgs &a, const Tile &t, const Pr
 }
 
 // Regenerate the 32 rows of a segment (tile rows tr_base .. tr_base + 31) for
-// the lane's node, zeros above its R.
+// the lane's node, zeros above its R.  No branch per row: a node live only in
+// the lower 16-row block enters the recurrence there from its seed, and rows
+// above a node's R run the recurrence on zeros.
 template <int PREC, int TM, int TN, int SPT>
 __device__ inline void gen_segment(const FusedArgs &a, const Producer &p, const ChunkIn<SPT> &in,
                                    int tr_base, int lane, const Stage<PREC, TM, TN> &sm) {
   constexpr int LD = LdsLayout<PREC>::LD;
   const int Rrel = in.R - a.lmin;                       // < 0 when the node has no row
   const bool liveA = in.R >= 0 && Rrel >= p.seg_hi;       // live through the upper 16 rows
-  const bool liveB = in.R >= 0 && Rrel >= p.seg_hi - 16;
-  double cur = liveB ? in.sd.x : 0.0, nxt = liveB ? in.sd.y : 0.0, ix = liveB ? in.nx : 0.0;
+  const bool liveB = in.R >= 0 && Rrel >= p.seg_hi - 16;  // live in the lower 16 rows
+  const double ix = liveB ? in.nx : 0.0;
   const double d2 = ix + ix;
+  double cur = liveA ? in.sd.x : 0.0, nxt = liveA ? in.sd.y : 0.0;
 #pragma unroll
   for (int half = 1; half >= 0; --half) {
-    const bool live = half ? liveA : liveB;
+    if (half == 0) {
+      cur = liveA ? cur : (liveB ? in.sd.x : 0.0);
+      nxt = liveA ? nxt : (liveB ? in.sd.y : 0.0);
+    }
     const int hi_row = p.seg_hi - 16 * (1 - half);  // l - lmin of the block's top row
     const int tr0 = tr_base + 16 * half;            // tile row of the block's bottom row
     double tt = 0.0;
 #pragma unroll
     for (int rr = 15; rr >= 0; --rr) {
-      float v = 0.f;
-      if (live) {
-        if (rr == 15 || rr == 7) tt = (double)(2 * (a.lmin + hi_row - 15 + rr) + 1) * ix;
-        v = (float)cur;
-        const double pv = rec_step(tt, cur, nxt);
-        nxt = cur;
-        cur = pv;
-        tt -= d2;
-      }
+      if (rr == 15 || rr == 7) tt = (double)(2 * (a.lmin + hi_row - 15 + rr) + 1) * ix;
+      const float v = PREC == 1 ? (float)cur : f32_opaque(cur);
+      const double pv = rec_step(tt, cur, nxt);
+      nxt = cur;
+      cur = pv;
+      tt -= d2;
       const int row = tr0 + rr;
       if (PREC == 1) {
         sm.Jf[row * LD + lane] = v;
@@ -347,9 +359,9 @@ __device__ inline void column_limits(const FusedArgs &a, const Tile &t, int wc, 
 #pragma unroll
   for (int j = 0; j < NBW; ++j) {
     const int cj = t.c0 + wc * NBW * 16 + 16 * j;
-    jlast[j] = (a.col_lmax && cj < t.ncol)
-                   ? ((a.col_lmax[a.col_off[t.r] + cj] - a.lmin) >> 4) - t.lb0
-                   : (cj < t.ncol ? a.nlb - 1 - t.lb0 : -1);
+    jlast[j] = __builtin_amdgcn_readfirstlane(  // uniform
+        (a.col_lmax && cj < t.ncol) ? ((a.col_lmax[a.col_off[t.r] + cj] - a.lmin) >> 4) - t.lb0
+                                    : (cj < t.ncol ? a.nlb - 1 - t.lb0 : -1));
   }
 }
 
@@ -481,7 +493,8 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
 
   Tile t;
   if (!tile_of_block<TM, TN>(a, tiles_m, tiles_n, kcount, t)) return;  // uniform
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
   const int g = lane >> 4, r16 = lane & 15;
   const int wr = w % WR, wc = w / WR;
   const Stage<PREC, TM, TN> sm(smem);
@@ -534,7 +547,8 @@ __global__ __launch_bounds__(512) void fused_ws_kernel(FusedArgs a, int tiles_m,
 
   Tile t;
   if (!tile_of_block<TM, TN>(a, tiles_m, tiles_n, kcount, t)) return;  // uniform
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the roles branch per wave
   const Chunks ch = active_chunks(a, t, lane);
   int c = next_chunk(ch.act0, ch.act1, 0);
 

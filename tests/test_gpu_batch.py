@@ -148,13 +148,21 @@ def test_batch_fused_matches_tables(torch_dev, ctx, prec, monkeypatch):
     assert plan.los_batch_info()["fused"] == 0
     plan.close()
     monkeypatch.delenv("LOS_BATCH_FUSED")
+    bad = []
     for shape in (0, 1, 2, 3, 6):
         monkeypatch.setenv("LOS_BATCH_SHAPE", str(shape))
         plan, _, cl = solve(torch_dev, ctx, b, prec, S=S)
         info = plan.los_batch_info()
         assert info["fused"] == 1 and info["fused_shape"] == shape and info["chunks"] == 1
-        np.testing.assert_array_equal(cl, base)
+        diff = np.argwhere(cl != base)
+        if diff.size:
+            m, pr, l = diff[0]
+            bad.append("shape %d: %d entries differ (first: model %d pair %d l-index %d, "
+                       "%.17g vs %.17g; l-index range %d..%d)"
+                       % (shape, len(diff), m, pr, l, cl[m, pr, l], base[m, pr, l],
+                          diff[:, 2].min(), diff[:, 2].max()))
         plan.close()
+    assert not bad, "; ".join(bad)
 
 
 def test_batch_fused_autotuned_vs_oracle(torch_dev, ctx):
