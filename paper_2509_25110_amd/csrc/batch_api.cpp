@@ -303,7 +303,7 @@ int enqueue(los_batch *b, const SolveArgs &s, hipStream_t st) {
   return LOS_OK;
 }
 
-// Fused pipeline: time the wide fused shapes (0..3 and 6) on two representative
+// Fused pipeline: time the wide fused shapes (0..3) on two representative
 // chunks after building their seeds once; keep the fastest total.
 // LOS_BATCH_SHAPE pins a shape; LOS_BATCH_TUNE=0 keeps shape 0.
 int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
@@ -335,8 +335,8 @@ int autotune_fused(los_batch *b, const SolveArgs &s, hipStream_t st) {
     (void)hipEventDestroy(t0);
     return hip_fail(e, "autotune: event");
   }
-  constexpr int kWide = 5;  // the shapes with at least 128 columns
-  constexpr int wide[kWide] = {0, 1, 2, 3, 6};
+  constexpr int kWide = 4;  // the shapes with at least 128 columns
+  constexpr int wide[kWide] = {0, 1, 2, 3};
   float total[kWide] = {};
   int rc = LOS_OK;
   for (int pi = 0; pi < nprobe && rc == LOS_OK; ++pi) {

@@ -147,9 +147,8 @@ struct FusedShape {
   int tm, tn;  // l rows x columns per workgroup
 };
 // Compiled shapes: 0 256x128 (waves 4x2), 1 128x128 (2x2), 2 256x128 (2x4),
-// 3 256x256 (2x4), 4 256x16 (8x1), 5 128x16 (4x1), 6 128x128 warp-specialised
-// (2x2 multiplying waves, 4 producing waves, two LDS stages).
-constexpr int kFusedShapeCount = 7;
+// 3 256x256 (2x4), 4 256x16 (8x1), 5 128x16 (4x1).
+constexpr int kFusedShapeCount = 6;
 FusedShape fused_shape_at(int i);
 size_t fused_seed_bytes_per_row(int nseg, int64_t ntp);
 void fused_workspace_at(FusedArgs &a, void *ws, int kcount);

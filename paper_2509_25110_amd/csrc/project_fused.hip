@@ -162,31 +162,50 @@ struct Tile {
   int64_t r, sbase, dbase;
 };
 
+// The tile (k rank kr, l tile tm, column tile tn); false when it has nothing
+// to compute (ki, r, tm, lb0 and tile_lo are set either way).
 template <int TM, int TN>
-__device__ inline bool tile_of_block(const FusedArgs &a, int tiles_m, int tiles_n, int kcount,
-                                     Tile &t) {
-  const int64_t per_row = (int64_t)tiles_m * tiles_n;
-  const int64_t L = blockIdx.x;
-  const int64_t q = L >> 3;
-  const int64_t kr = (L & 7) + 8 * (q / per_row);
-  if (kr >= kcount) return false;
-  t.tm = (int)(q % per_row % tiles_m);
-  const int tn = (int)(q % per_row / tiles_m);
+__device__ inline bool tile_at(const FusedArgs &a, int kcount, int64_t kr, int tm, int tn, Tile &t) {
+  t.tm = tm;
   t.ki = kcount - 1 - (int)kr;
   t.r = a.k0 + t.ki;
+  t.lb0 = tm * (TM / 16);
+  t.tile_lo = 16 * t.lb0;  // first row of the tile (l - lmin)
   t.ncol = a.col_cnt ? a.col_cnt[t.r] : a.ncol;
   t.c0 = tn * TN;
-  if (t.c0 >= t.ncol) return false;
-  t.lb0 = t.tm * (TM / 16);
-  t.lb_last = a.nlb - 1;
-  if (a.col_lmax) t.lb_last = min(t.lb_last, (a.col_lmax[a.col_off[t.r] + t.c0] - a.lmin) >> 4);
-  if (t.lb0 > t.lb_last) return false;
-  t.tile_lo = 16 * t.lb0;                        // first row of the tile (l - lmin)
-  t.top_cap = 16 * t.lb_last + 15 - t.tile_lo;   // last tile row any column needs
   t.sbase = a.col_off ? a.col_off[t.r] * a.s_cstride : t.r * a.s_kstride;
   t.dbase = a.col_off ? (a.col_off[t.r] - a.col_base) * (int64_t)a.nl
                       : t.r * (int64_t)a.nl * t.ncol;
+  if (t.c0 >= t.ncol) return false;
+  t.lb_last = a.nlb - 1;
+  if (a.col_lmax) t.lb_last = min(t.lb_last, (a.col_lmax[a.col_off[t.r] + t.c0] - a.lmin) >> 4);
+  if (t.lb0 > t.lb_last) return false;
+  t.top_cap = 16 * t.lb_last + 15 - t.tile_lo;  // last tile row any column needs
   return true;
+}
+
+// The work item of this block: XCD x = L % 8 takes the rows of rank x, x + 8,
+// ... (rank 0 = largest k, the most work); within a row the l tiles of one
+// column tile follow each other (they read the same S columns, kept in that
+// XCD's L2).
+__device__ inline bool block_item(int tiles_m, int tiles_n, int kcount, int64_t &kr, int &tm,
+                                  int &tn) {
+  const int64_t per_row = (int64_t)tiles_m * tiles_n;
+  const int64_t L = blockIdx.x;
+  const int64_t q = L >> 3;
+  kr = (L & 7) + 8 * (q / per_row);
+  tm = (int)(q % per_row % tiles_m);
+  tn = (int)(q % per_row / tiles_m);
+  return kr < kcount;
+}
+
+template <int TM, int TN>
+__device__ inline bool tile_of_block(const FusedArgs &a, int tiles_m, int tiles_n, int kcount,
+                                     Tile &t) {
+  int64_t kr;
+  int tm, tn;
+  if (!block_item(tiles_m, tiles_n, kcount, kr, tm, tn)) return false;
+  return tile_at<TM, TN>(a, kcount, kr, tm, tn, t);
 }
 
 // Active chunks: those whose largest top row reaches the tile's first row, as
@@ -259,16 +278,28 @@ __device__ inline void load_chunk_in(const FusedArgs &a, const Tile &t, const Pr
   in.R = a.rtop[p.rowb + n];
   in.nx = a.nix[p.rowb + n];
   if (p.seg_ok) in.sd = p.seedp[n];  // read whatever the node's R; used only below R
+  // A chunk wholly inside the tau grid with 16-byte aligned columns loads its
+  // pieces as 16-byte vectors with no branch (columns past ncol read column 0
+  // and are zeroed); the last, ragged chunk goes element by element.
+  if (p.s_vec && (c + 1) * KB <= a.ntau) {  // uniform
 #pragma unroll
-  for (int q = 0; q < SPT; ++q) {
-    if (SP % NTH != 0 && q * NTH + pt >= SP) break;
-    const int e = (q * NTH + pt) * 4;  // element within [TN][KB]
-    const int col = e / KB, nn = e % KB;
-    const int cg = t.c0 + col, ng = c * KB + nn;
-    const float *src = a.S + t.sbase + (int64_t)(cg < t.ncol ? cg : 0) * a.s_cstride + ng;
-    if (cg < t.ncol && p.s_vec && ng + 4 <= a.ntau) {
-      in.sv[q] = *(const float4 *)src;
-    } else {
+    for (int q = 0; q < SPT; ++q) {
+      if (SP % NTH != 0 && q * NTH + pt >= SP) break;
+      const int e = (q * NTH + pt) * 4;  // element within [TN][KB]
+      const int col = e / KB, nn = e % KB;
+      const int cg = t.c0 + col;
+      const float4 v = *(const float4 *)(a.S + t.sbase + (int64_t)(cg < t.ncol ? cg : 0) * a.s_cstride +
+                                         c * KB + nn);
+      in.sv[q] = cg < t.ncol ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      if (SP % NTH != 0 && q * NTH + pt >= SP) break;
+      const int e = (q * NTH + pt) * 4;
+      const int col = e / KB, nn = e % KB;
+      const int cg = t.c0 + col, ng = c * KB + nn;
+      const float *src = a.S + t.sbase + (int64_t)(cg < t.ncol ? cg : 0) * a.s_cstride + ng;
       float t4[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) t4[u] = (cg < t.ncol && ng + u < a.ntau) ? src[u] : 0.f;
@@ -527,82 +558,6 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
   store_acc<MBW, NBW, WR>(a, t, acc, wr, wc, g, r16);
 }
 
-// Warp-specialised form with two LDS stages: 8 waves, of which waves 0..3
-// (2 x 2) only multiply and waves 4..7 only produce.  While the multiplying
-// waves work on chunk c from one stage, the producing waves regenerate the
-// J segments of the next active chunk (one 32-row segment per wave) and stage
-// its S columns into the other stage, then issue the loads of the chunk after
-// it; one barrier per chunk.  Each SIMD runs one wave of each kind, so the
-// FP64 recurrence, the S traffic and the barrier waits overlap the matrix
-// cores.  The products and their order are those of fused_gemm_kernel with
-// WR = WC = 2.
-template <int PREC, int MBW, int NBW>
-__global__ __launch_bounds__(512) void fused_ws_kernel(FusedArgs a, int tiles_m, int tiles_n,
-                                                       int kcount) {
-  constexpr int WR = 2, NP = 256;  // multiplying waves 2 x 2; producing threads
-  constexpr int TM = WR * MBW * 16, TN = 2 * NBW * 16;
-  static_assert(TM / 32 == 4, "one 32-row segment per producing wave");
-  constexpr size_t STAGE = LdsLayout<PREC>::bytes(TM, TN);
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-
-  Tile t;
-  if (!tile_of_block<TM, TN>(a, tiles_m, tiles_n, kcount, t)) return;  // uniform
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the roles branch per wave
-  const Chunks ch = active_chunks(a, t, lane);
-  int c = next_chunk(ch.act0, ch.act1, 0);
-
-  if (w >= 4) {
-    // producing waves: chunk cn into stage st, then the loads of the next one
-    const int pw = w - 4, pt = tid - 4 * 64;
-    const Producer p = producer_of(a, t, t.tm * 4 + pw);
-    ChunkIn<SPieces<TN, NP>::SPT> in;
-    auto produce = [&](int cp, int st) {
-      const Stage<PREC, TM, TN> sm(smem + st * STAGE);
-      const int top_tr = chunk_top(a, t, ch, cp);
-      if (p.seg_ok && 32 * pw <= top_tr) gen_segment(a, p, in, 32 * pw, lane, sm);
-      store_s<PREC, TM, TN, NP>(in, pt, sm);
-      const int cq = next_chunk(ch.act0, ch.act1, cp + 1);
-      if (cq >= 0) load_chunk_in<TN, NP>(a, t, p, cq, lane, pt, in);
-    };
-    if (c >= 0) {
-      load_chunk_in<TN, NP>(a, t, p, c, lane, pt, in);
-      produce(c, 0);
-    }
-    __syncthreads();
-    int st = 0;
-    while (c >= 0) {
-      const int cn = next_chunk(ch.act0, ch.act1, c + 1);
-      if (cn >= 0) produce(cn, st ^ 1);
-      __syncthreads();
-      st ^= 1;
-      c = cn;
-    }
-    return;
-  }
-
-  // multiplying waves
-  const int g = lane >> 4, r16 = lane & 15;
-  const int wr = w % WR, wc = w / WR;
-  f4 acc[MBW][NBW];
-#pragma unroll
-  for (int i = 0; i < MBW; ++i)
-#pragma unroll
-    for (int j = 0; j < NBW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  int jlast[NBW];
-  column_limits(a, t, wc, jlast);
-  __syncthreads();  // the first chunk is staged
-  int st = 0;
-  while (c >= 0) {
-    const Stage<PREC, TM, TN> sm(smem + st * STAGE);
-    mfma_chunk<PREC, TM, TN, MBW, NBW, WR>(acc, jlast, wr, wc, chunk_top(a, t, ch, c), g, r16, sm);
-    __syncthreads();
-    st ^= 1;
-    c = next_chunk(ch.act0, ch.act1, c + 1);
-  }
-  store_acc<MBW, NBW, WR>(a, t, acc, wr, wc, g, r16);
-}
-
 // Sets the large-LDS limit of a kernel once per device (a per-device function
 // attribute).
 template <typename K>
@@ -643,21 +598,6 @@ hipError_t launch_fused_t(const FusedArgs &a, int kcount, int max_ncol, hipStrea
   return hipGetLastError();
 }
 
-template <int PREC, int MBW, int NBW>
-hipError_t launch_ws_t(const FusedArgs &a, int kcount, int max_ncol, hipStream_t s) {
-  constexpr int TM = 2 * MBW * 16, TN = 2 * NBW * 16;
-  int tiles_m, tiles_n;
-  const int64_t grid = fused_grid(a, kcount, max_ncol, TM, TN, tiles_m, tiles_n);
-  if (grid > 0x7fffffff || grid < 1) return hipErrorInvalidValue;
-  const size_t lds = 2 * LdsLayout<PREC>::bytes(TM, TN);
-  auto kern = fused_ws_kernel<PREC, MBW, NBW>;
-  static bool done[64] = {};
-  hipError_t e = allow_lds(kern, lds, done);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(512), lds, s, a, tiles_m, tiles_n, kcount);
-  return hipGetLastError();
-}
-
 template <int PREC>
 hipError_t launch_fused_p(const FusedArgs &a, int shape, int kcount, int max_ncol,
                           hipStream_t s) {
@@ -668,7 +608,6 @@ hipError_t launch_fused_p(const FusedArgs &a, int shape, int kcount, int max_nco
     case 3: return launch_fused_t<PREC, 2, 4, 8, 4>(a, kcount, max_ncol, s);  // 256 x 256
     case 4: return launch_fused_t<PREC, 8, 1, 2, 1>(a, kcount, max_ncol, s);  // 256 x 16
     case 5: return launch_fused_t<PREC, 4, 1, 2, 1>(a, kcount, max_ncol, s);  // 128 x 16
-    case 6: return launch_ws_t<PREC, 4, 4>(a, kcount, max_ncol, s);           // 128 x 128, 2 stages
     default: return hipErrorInvalidValue;
   }
 }
@@ -677,7 +616,7 @@ hipError_t launch_fused_p(const FusedArgs &a, int shape, int kcount, int max_nco
 
 FusedShape fused_shape_at(int i) {
   static const FusedShape shapes[kFusedShapeCount] = {
-      {256, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 16}, {128, 16}, {128, 128}};
+      {256, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 16}, {128, 16}};
   return shapes[i];
 }
 

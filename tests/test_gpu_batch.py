@@ -138,7 +138,7 @@ def test_batch_tiles_agree(torch_dev, ctx, mb, nc, monkeypatch):
 def test_batch_fused_matches_tables(torch_dev, ctx, prec, monkeypatch):
     """The default pipeline (Bessel tiles regenerated in LDS) gives bitwise the C_l of the table
     pipeline (same values, same accumulation order; both one chunk here), for every wide fused
-    tile shape (6: the warp-specialised kernel with two LDS stages)."""
+    tile shape."""
     b = small_batch(n=9, seed=23, lmax_range=(100, 700), nk_range=(40, 200), master_nk=300,
                     master_kmax=0.12, ntau=900)
     monkeypatch.setenv("LOS_BATCH_FUSED", "0")
@@ -149,7 +149,7 @@ def test_batch_fused_matches_tables(torch_dev, ctx, prec, monkeypatch):
     plan.close()
     monkeypatch.delenv("LOS_BATCH_FUSED")
     bad = []
-    for shape in (0, 1, 2, 3, 6):
+    for shape in (0, 1, 2, 3):
         monkeypatch.setenv("LOS_BATCH_SHAPE", str(shape))
         plan, _, cl = solve(torch_dev, ctx, b, prec, S=S)
         info = plan.los_batch_info()
@@ -161,6 +161,28 @@ def test_batch_fused_matches_tables(torch_dev, ctx, prec, monkeypatch):
                        "%.17g vs %.17g; l-index range %d..%d)"
                        % (shape, len(diff), m, pr, l, cl[m, pr, l], base[m, pr, l],
                           diff[:, 2].min(), diff[:, 2].max()))
+        plan.close()
+    assert not bad, "; ".join(bad)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_batch_fused_shapes_many_columns(torch_dev, ctx, prec, monkeypatch):
+    """Rows with up to 300 packed columns (three 128-column tiles, the last partly filled, and
+    two 256-column tiles): every wide fused shape gives bitwise the C_l of the 128 x 128 one."""
+    b = small_batch(n=100, seed=29, lmax_range=(60, 400), nk_range=(60, 150), master_nk=160,
+                    master_kmax=0.08, ntau=700)
+    assert np.max(np.bincount(b.k_index)) * 3 > 256    # a row with three column tiles
+    monkeypatch.setenv("LOS_BATCH_SHAPE", "1")
+    plan, S, base = solve(torch_dev, ctx, b, prec)
+    plan.close()
+    bad = []
+    for shape in (0, 2, 3):
+        monkeypatch.setenv("LOS_BATCH_SHAPE", str(shape))
+        plan, _, cl = solve(torch_dev, ctx, b, prec, S=S)
+        assert plan.los_batch_info()["fused_shape"] == shape
+        n = int(np.sum(cl != base))
+        if n:
+            bad.append("shape %d: %d entries differ" % (shape, n))
         plan.close()
     assert not bad, "; ".join(bad)
 
