@@ -347,7 +347,8 @@ def run_batch(args):
         m = 3
         d = b.draws[m]
         wlm = inputs.model_workload(d)
-        rows = np.arange(0, wlm.nk, 32)
+        stride = args.cpu_stride or 1                   # all rows of the model: about 10 s
+        rows = np.arange(0, wlm.nk, stride)
         Sm = np.ascontiguousarray(wlm.S[:, rows, :])
         t0 = time.perf_counter()
         oracle.project(wlm.lmin, wlm.lmax, wlm.k[rows], wlm.tau, wlm.tau0, wlm.w_tau, Sm)
@@ -356,9 +357,9 @@ def run_batch(args):
         total = dense / rate
         out["cpu_baseline"] = {"value": b.nmodels / total, "unit": "spectra/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
-                               "sample": "model %d, every 32nd of its %d k rows, all l and tau: "
-                                         "%.1f s; scaled by the batch's dense (k, tau, l) count"
-                                         % (m, wlm.nk, dt)}
+                               "sample": "model %d, %d of its %d k rows (stride %d), all l and "
+                                         "tau: %.1f s; scaled by the batch's dense (k, tau, l) "
+                                         "count" % (m, rows.size, wlm.nk, stride, dt)}
     del S
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -494,6 +495,17 @@ def run_emulator(args):
         del cfb
     assert not bool(flag4.any().item())
     effective = n / (t_emu + t_fb)
+    # the same 4096 models solved by the batched solver alone (plan + solve): the time the
+    # emulator competes with, and the reference for the rows it kept
+    _, call, t_all = solve_models(ctx, new, 2, torch, timed="plan+solve")
+    got, want = cl.cpu().numpy(), call.cpu().numpy()
+    del call
+    keep = np.setdiff1d(np.arange(n), rows)
+    kept_err = None
+    if keep.size:
+        sc = np.abs(want[keep]).copy()
+        sc[:, 2] = np.sqrt(want[keep][:, 0] * want[keep][:, 1])
+        kept_err = np.max(np.abs(got[keep] - want[keep]) / sc, axis=(1, 2))
     emu_rate = n / (infer_ms * 1e-3)
     fp64_rate = len(te) / t64
     flops = n * 2.0 * (emu.nparams + 4 * 96 * nl) * emu.members
@@ -520,6 +532,11 @@ def run_emulator(args):
                      "work": "4096 x 4 members x 2 x (MLP params + 4 x 96 x %d)" % nl},
         "fallback_threshold": thr, "fallback_models": merged,
         "fallback_fraction": merged / n, "fallback_s": t_fb, "emulate_s": t_emu,
+        "batched_solver_alone_spectra_per_s": n / t_all,
+        "gain_vs_batched_solver": t_all / (t_emu + t_fb),
+        "kept_models_err_vs_batched_solver": None if kept_err is None else {
+            "median": float(np.median(kept_err)), "max": float(np.max(kept_err)),
+            "above_threshold": int(np.sum(kept_err > thr))},
         "emulator_only_spectra_per_s": emu_rate,
         "fp64_plain_path_spectra_per_s": fp64_rate,
         "speedup_vs_fp64_plain_path": effective / fp64_rate,
@@ -553,7 +570,8 @@ def main():
                     help="default fp32 for C4, fp64 for C1-C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0,
-                    help="oracle sample: every n-th k row (default 1 for C2, 4 for C3)")
+                    help="oracle sample: every n-th k row (default 1 for C2, T2 and the C4 model, "
+                         "4 for C3)")
     ap.add_argument("--emu-train", type=int, default=4096, help="C5: training spectra")
     ap.add_argument("--emu-epochs", type=int, default=300, help="C5: training epochs")
     ap.add_argument("--emu-heldout", type=int, default=32,
