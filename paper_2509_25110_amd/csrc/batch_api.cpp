@@ -48,7 +48,7 @@ struct los_batch {
   // device
   int64_t *d_rows = nullptr, *d_col_off = nullptr, *d_pos_col = nullptr, *d_koff = nullptr,
           *d_jr = nullptr;
-  int *d_col_cnt = nullptr, *d_col_lmax = nullptr, *d_lmax = nullptr;
+  int *d_col_cnt = nullptr, *d_col_lmax = nullptr, *d_lmax = nullptr, *d_order = nullptr;
   float *J = nullptr, *D = nullptr;
   int *top = nullptr;
   // fused pipeline: seeds workspace (J unused)
@@ -93,7 +93,7 @@ void free_plan(los_batch *b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   // `top` lives inside the J allocation
   void *ptrs[] = {b->d_rows, b->d_col_off, b->d_pos_col, b->d_koff, b->d_jr, b->d_col_cnt,
-                  b->d_col_lmax, b->d_lmax, b->J, b->D, b->seedws};
+                  b->d_col_lmax, b->d_lmax, b->d_order, b->J, b->D, b->seedws};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -291,6 +291,7 @@ int enqueue(los_batch *b, const SolveArgs &s, hipStream_t st) {
     ca.lmax = b->d_lmax;
     ca.koff = b->d_koff;
     ca.jr = b->d_jr;
+    ca.order = b->d_order + (size_t)c * b->nmodels;
     ca.pos_col = b->d_pos_col;
     ca.col_base = b->chunk_col0[c];
     ca.D = b->D;
@@ -627,6 +628,18 @@ int los_batch_create(los_ctx *ctx, int32_t nmodels, int32_t nsrc, const int32_t 
     }
   }
 
+  // per chunk, the models with the most rows in it first: the C_l launch
+  // starts its longest workgroups first
+  std::vector<int> cl_order((size_t)b->nchunks * nmodels);
+  for (int c = 0; c < b->nchunks; ++c) {
+    int *o = cl_order.data() + (size_t)c * nmodels;
+    for (int m = 0; m < nmodels; ++m) o[m] = m;
+    const int64_t *jc = jr.data() + (size_t)c * nmodels * 2;
+    std::stable_sort(o, o + nmodels, [jc](int x, int y) {
+      return jc[2 * x + 1] - jc[2 * x] > jc[2 * y + 1] - jc[2 * y];
+    });
+  }
+
   std::vector<int> lmax_v(lmax, lmax + nmodels);
   std::vector<int64_t> koff_v(koff, koff + nmodels + 1);
   int rc = LOS_OK;
@@ -638,6 +651,7 @@ int los_batch_create(los_ctx *ctx, int32_t nmodels, int32_t nsrc, const int32_t 
   if (rc == LOS_OK) rc = dev_copy(&b->d_koff, koff_v.data(), koff_v.size());
   if (rc == LOS_OK) rc = dev_copy(&b->d_lmax, lmax_v.data(), lmax_v.size());
   if (rc == LOS_OK) rc = dev_copy(&b->d_jr, jr.data(), jr.size());
+  if (rc == LOS_OK) rc = dev_copy(&b->d_order, cl_order.data(), cl_order.size());
   if (rc == LOS_OK) {
     hipError_t e = b->fused ? hipMalloc(&b->seedws, srow * (size_t)b->kc)
                             : hipMalloc((void **)&b->J, jrow * (size_t)b->kc);
@@ -793,6 +807,7 @@ int los_batch_solve_timed(los_batch *plan, double tau0, const double *k_master,
     ca.lmax = plan->d_lmax;
     ca.koff = plan->d_koff;
     ca.jr = plan->d_jr;
+    ca.order = plan->d_order + (size_t)c * plan->nmodels;
     ca.pos_col = plan->d_pos_col;
     ca.col_base = plan->chunk_col0[c];
     ca.D = plan->D;

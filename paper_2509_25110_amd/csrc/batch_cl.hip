@@ -18,7 +18,7 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(double *p, int64_t n) {
 
 template <int NSRC>
 __global__ __launch_bounds__(256) void batch_cl_kernel(BatchClArgs a) {
-  const int m = blockIdx.y;
+  const int m = a.order[blockIdx.y];  // longest workgroups dispatched first
   const int lr = blockIdx.x * 256 + threadIdx.x;  // l - lmin
   if (lr + a.lmin > a.lmax[m]) return;
   const int64_t *jr = a.jr + ((int64_t)a.chunk * a.nmodels + m) * 2;

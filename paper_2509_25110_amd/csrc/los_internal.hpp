@@ -164,6 +164,7 @@ struct BatchClArgs {
   const int *lmax;         // [nmodels]
   const int64_t *koff;     // [nmodels + 1] first k position of each model
   const int64_t *jr;       // [nchunks][nmodels][2] j range of each model in each chunk
+  const int *order;        // [nmodels] this chunk's models, the most rows first
   const int64_t *pos_col;  // [koff[nmodels]] packed column of (model, j), source 0
   int64_t col_base;
   const float *D;
