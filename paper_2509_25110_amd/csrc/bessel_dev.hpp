@@ -36,6 +36,14 @@ __host__ __device__ inline int ltop_of(double x) {
   return (int)floor(x + 14.2 * cbrt(x) + 9.5);
 }
 
+// Band cut of the MFMA (FP32 / split-BF16x3) projections: above
+// x + 9 x^(1/3) + 4, |j_l(x)| stays below 1.2e-12 of its largest value over l
+// (checked for x = 1 .. 14000), far below the FP32 rounding of the values
+// kept; the seeds still start at ltop(x) and run down to the cut.
+__host__ __device__ inline int ltop_mfma_of(double x) {
+  return (int)floor(x + 9.0 * cbrt(x) + 4.0);
+}
+
 // From this x on, the pair at the band edge comes from debye_j; below it the
 // upward and Miller runs are short.
 constexpr double kXDebye = 64.0;
@@ -162,9 +170,9 @@ __host__ __device__ inline void run_down(double &hn, double &hc, int l0, int l1,
 
 // Normalised pair at a node's top row, the start of a descending sweep over
 // rows lmin..lmax in 16-row blocks (Bessel tables and the fused projection).
-// For x = k chi (x >= kXTiny) and weight wt: R is the top row of the 16-row
-// block (counted from lmin) that holds min(ltop(x), lmax), and on return
-// (cur, nxt) = wt (j_R, j_{R+1}):
+// For x = k chi (x >= kXTiny), weight wt and band cut lcut <= ltop(x) (rows
+// above it are dropped): R is the top row of the 16-row block (counted from
+// lmin) that holds min(lcut, lmax), and on return (cur, nxt) = wt (j_R, j_{R+1}):
 //   * x >= lmax + 1: upward recurrence from j_0 = sin x / x, j_{-1} = cos x / x
 //     (stable on the oscillatory side) up to l = R + 1 (R is at most 15 rows
 //     past lmax; those rows are never stored);
@@ -175,13 +183,13 @@ __host__ __device__ inline void run_down(double &hn, double &hc, int l0, int l1,
 //     there by j_m (near the last maximum in l, never near a zero).
 // Returns R, or -1 when no row in [lmin, lmax] is inside the band.
 __host__ __device__ inline int node_top_pair(double x, double ix, double wt, int lmin, int lmax,
-                                             double &cur, double &nxt) {
+                                             int lcut, double &cur, double &nxt) {
   cur = 0.0;
   nxt = 0.0;
   const int m = (int)x;
   const int L0 = ltop_of(x);
   if (m < lmax + 1 && x >= kXDebye) {
-    const int Rc = min(L0, lmax);
+    const int Rc = min(lcut, lmax);
     if (Rc < lmin) return -1;
     const int R = lmin + (Rc - lmin) / 16 * 16 + 15;
     const int Ld = max(L0, R);
@@ -202,7 +210,7 @@ __host__ __device__ inline int node_top_pair(double x, double ix, double wt, int
   }
   run_up(p, q, 0, m, ix);
   const double jm = q;
-  const int Rc = min(L0, lmax);
+  const int Rc = min(lcut, lmax);
   if (Rc < lmin) return -1;
   const int R = lmin + (Rc - lmin) / 16 * 16 + 15;
   double hn = 0.0, hc = 1.0;  // J^_{l+1}, J^_l

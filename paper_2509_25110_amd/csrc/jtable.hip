@@ -56,11 +56,11 @@ __global__ __launch_bounds__(256) void jtable_kernel(JTableArgs a) {
     const double wt = a.w[n];
     if (x >= kXTiny && wt != 0.0) {
       ix = 1.0 / x;
-      // R is the top row of the 16-row block holding min(ltop(x), lmax): a lane
-      // is then live either throughout a block or not at all.  Rows between
-      // the band edge and R hold values below the band cut; rows past lmax
-      // (at most 15, inside the padded table) are never stored by the product.
-      R = node_top_pair(x, ix, wt, a.lmin, a.lmax, cur, nxt);
+      // R is the top row of the 16-row block holding min(ltop_mfma(x), lmax): a
+      // lane is then live either throughout a block or not at all.  Rows past
+      // lmax (at most 15, inside the padded table) are never stored by the
+      // product.
+      R = node_top_pair(x, ix, wt, a.lmin, a.lmax, ltop_mfma_of(x), cur, nxt);
     }
   }
 

@@ -2,8 +2,9 @@
 // Sec. 2.1 Eq. 2-3; per k the tau sum is Delta_k[l][c] = sum_n J_k[l][n] S_k[n][c]
 // with J_k[l][n] = w_n j_l(k chi_n)), in two kernels per chunk of k rows:
 //
-// jseed_kernel (FP64, one lane per tau node): the node's top row R and the
-//   pair w (j_R, j_{R+1}) (node_top_pair), then ONE descending sweep that
+// jseed_kernel (FP64, one lane per tau node): the node's top row R (below the
+//   MFMA band cut ltop_mfma) and the pair w (j_R, j_{R+1}) (node_top_pair),
+//   then ONE descending sweep that
 //   leaves, at the top row of every 32-row segment at or below R, the pair
 //   (w j_T, w j_{T+1}), T = min(R, segment top), in a seed table; also 1/x
 //   and R per node and the largest R of every chunk of 64 nodes.  Nothing of
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void jseed_kernel(FusedArgs a) {
     const double wt = a.w[n];
     if (x >= kXTiny && wt != 0.0) {
       ix = 1.0 / x;
-      R = node_top_pair(x, ix, wt, a.lmin, a.lmax, cur, nxt);
+      R = node_top_pair(x, ix, wt, a.lmin, a.lmax, ltop_mfma_of(x), cur, nxt);
     }
   }
   // every lane of the wave is here (ntp is a multiple of 64): the wave's 64

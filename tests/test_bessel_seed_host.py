@@ -8,7 +8,10 @@ sqrt(pi/(2x)) J_{l+1/2}(x):
 * node_top_pair: the (unweighted) pair (j_R, j_{R+1}) at a node's top row R for every branch
   (Debye seed for 64 <= x < lmax + 1, upward recurrence for x >= lmax + 1, Miller's
   recurrence normalised by the upward value below 64), with R the top row of the 16-row
-  block holding min(ltop(x), lmax).
+  block holding min(cut(x), lmax), for both band cuts: the FP64 one ltop(x) and the MFMA
+  paths' ltop_mfma(x) = floor(x + 9 x^(1/3) + 4) (the seed still starts at ltop and runs
+  down to R);
+* the MFMA band cut drops no value above 1.2e-12 of the largest |j_l(x)| over l.
 Bound 1e-13: relative for the Debye values themselves (their own error is about |eta| ~ 60
 ulps of e^eta); for the pair at R relative to the largest |j_l| over the rows lmin..R+1 the
 sweep covers (a Miller pair at the band edge carries the seed's error there, which the
@@ -36,7 +39,7 @@ def hc():
     lib = ctypes.CDLL(LIB)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     lib.los_hostcheck_debye_j.argtypes = [i64, vp, vp, vp]
-    lib.los_hostcheck_node_top_pair.argtypes = [i64, vp, i32, i32, vp, vp, vp]
+    lib.los_hostcheck_node_top_pair.argtypes = [i64, vp, i32, i32, i32, vp, vp, vp]
     return lib
 
 
@@ -49,6 +52,10 @@ def jl_mp(l, x):
 
 def ltop(x):
     return int(math.floor(x + 14.2 * np.cbrt(x) + 9.5))
+
+
+def ltop_mfma(x):
+    return int(math.floor(x + 9.0 * np.cbrt(x) + 4.0))
 
 
 def debye(hc, ls, xs):
@@ -90,18 +97,20 @@ def test_debye_series_branch_boundary(hc):
         assert abs(g / jl_mp(l, x) - 1) <= 1e-13, (l, x)
 
 
+@pytest.mark.parametrize("mfma", [0, 1], ids=["fp64_cut", "mfma_cut"])
 @pytest.mark.parametrize("lmin,lmax", [(2, 2500), (2, 300), (37, 1000), (1, 64)])
-def test_node_top_pair_branches(hc, lmin, lmax):
+def test_node_top_pair_branches(hc, lmin, lmax, mfma):
     xs = np.array([0.5, 3.0, 20.0, 63.9, 64.0, 200.0, 0.8 * lmax, lmax - 30.0, lmax - 0.5,
                    lmax + 1.0, lmax + 1.5, 1.7 * lmax + 3.3], dtype=np.float64)
     xs = xs[xs > 0]
     n = xs.size
     cur, nxt = np.empty(n), np.empty(n)
     R = np.empty(n, dtype=np.int32)
-    hc.los_hostcheck_node_top_pair(n, xs.ctypes.data, lmin, lmax, cur.ctypes.data,
+    hc.los_hostcheck_node_top_pair(n, xs.ctypes.data, lmin, lmax, mfma, cur.ctypes.data,
                                    nxt.ctypes.data, R.ctypes.data)
+    cut = ltop_mfma if mfma else ltop
     for i, x in enumerate(xs):
-        rc = min(ltop(x), lmax) if math.floor(x) < lmax + 1 else lmax
+        rc = min(cut(x), lmax) if math.floor(x) < lmax + 1 else lmax
         want_R = lmin + (rc - lmin) // 16 * 16 + 15 if rc >= lmin else -1
         assert R[i] == want_R, (x, R[i], want_R)
         if want_R < 0:
@@ -116,3 +125,18 @@ def test_node_top_pair_branches(hc, lmin, lmax):
             ref = jl_mp(l, x)
             sc = scale * tol / 1e-13
             assert abs(got - ref) <= 1e-13 * float(sc), (lmin, lmax, x, l, got, float(ref))
+
+
+def test_mfma_band_cut_tail():
+    """Above ltop_mfma(x) no |j_l(x)| exceeds 1.2e-12 of the largest over l (scipy's
+    spherical_jn, accurate to a few ulps of the peak here), and the cut is below ltop."""
+    worst = 0.0
+    for x in (0.3, 1.0, 5.0, 20.0, 63.9, 64.0, 100.0, 300.0, 1000.0, 3000.0, 6000.0, 14000.0):
+        ls = np.arange(0, int(x + 20 * np.cbrt(x) + 40))
+        j = spherical_jn(ls, x)
+        peak = float(np.max(np.abs(j)))
+        tail = float(np.max(np.abs(j[ltop_mfma(x) + 1:]))) / peak
+        worst = max(worst, tail)
+        assert tail <= 1.2e-12, (x, tail)
+        assert ltop_mfma(x) <= ltop(x)
+    print("largest dropped |j_l| / peak: %.2e" % worst)
