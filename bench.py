@@ -168,10 +168,11 @@ def golden_error_c4(cl, b):
     return worst
 
 
-def batch_traffic(kernel, workload):
+def batch_traffic(kernel, workload, launches, prec_name):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter profile of the
-    same kernel source (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
-    plain device copy of known size); None when there is none or the source has changed."""
+    same kernel source, precision and number of launches per step (FETCH_SIZE and WRITE_SIZE,
+    each scaled by what the counter reads for a plain device copy of known size); None when
+    there is none or any of those has changed."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_%s.txt" % (kernel.replace("_kernel", ""), workload))
     src = os.path.join(ROOT, "paper_2509_25110_amd", "csrc", "project_fused.hip")
@@ -183,7 +184,9 @@ def batch_traffic(kernel, workload):
             key, val = line.split(":", 1)
             fields[key.strip()] = val.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    if (fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields
+            or fields.get("launches_per_step") != str(launches)
+            or fields.get("precision") != prec_name):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -278,7 +281,7 @@ def run_batch(args):
     plan.close()
     msum = summary(main, "bf16x3_mfma" if prec_name == "bf16x3" else "fp32_mfma")
     roof = dict(msum["roofline"])
-    roof["traffic"] = batch_traffic(roof["kernel"], "C4")
+    roof["traffic"] = batch_traffic(roof["kernel"], "C4", main["launches"], prec_name)
     roof["work"] = ("2 x 3 sources x %d TP entries (useful FP32-equivalent flops) per step, "
                     "over %d launches" % (tp, main["launches"]))
     roof["peak_note"] = ("bf16x3: 2516.6 TF dense bf16 / 3" if prec_name == "bf16x3" else

@@ -322,7 +322,7 @@ int los_interp_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, co
  * LOS_BATCH_FUSED=0 at plan creation selects whole FP32 tables instead.
  *
  * los_batch_create (host arrays; allocates the plan's device tables and a
- * workspace of at most LOS_BATCH_MIB MiB (default 8192) of seeds plus
+ * workspace of at most LOS_BATCH_MIB MiB (default 32768) of seeds plus
  * products -- with LOS_BATCH_FUSED=0, LOS_JTAB_MIB MiB (default 4096) of
  * Bessel tables plus one chunk of products): lmax[nmodels] in [2, 16000]; koff[nmodels+1] with koff[0] = 0
  * and koff[m+1] > koff[m]; k_index[koff[nmodels]] in [0, nk_master);
