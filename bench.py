@@ -372,25 +372,27 @@ EMU_LO = np.array([260.0, 15.0, 0.0, 0.92, 2.9])     # tau*, width, ISW amp, n_s
 EMU_HI = np.array([300.0, 25.0, 0.2, 1.0, 3.2])
 
 
-def solve_models(ctx, draws, prec, torch, chunk=256, timed=None):
+def solve_models(ctx, draws, prec, torch, chunk=256, timed=None, tt_only=False):
     """Batched solve of drawn models (all on the full master grid, l_max 5000) in plans of
-    `chunk` models; returns (params [n, 5], cl [n, 4, 4999] on the device, seconds).  The
-    sources of each plan are generated on the device before its timed part; `timed` lists what
-    the seconds include: "solve" (the solve call) or "plan+solve" (plan creation too)."""
+    `chunk` models; returns (params [n, 5], cl [n, 4, 4999] on the device, seconds), or with
+    tt_only the temperature source alone and cl [n, 1, 4999] (TT).  The sources of each plan
+    are generated on the device before its timed part; `timed` lists what the seconds include:
+    "solve" (the solve call) or "plan+solve" (plan creation too)."""
     from paper_2509_25110_amd import inputs
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     out, secs = [], 0.0
     with_plan = timed == "plan+solve"
     for c0 in range(0, len(draws), chunk):
         b = inputs.batch_inputs(draws[c0:c0 + chunk])
+        srcs = (0,) if tt_only else (0, 1, 2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, b.pairs,
-                                    prec=prec)
+        plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau,
+                                    [(0, 0)] if tt_only else b.pairs, prec=prec, nsrc=len(srcs))
         col, ncols = plan.los_batch_columns()
         t_plan = time.perf_counter() - t0
         S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
-        inputs.batch_sources_device(b, col, S, torch)
+        inputs.batch_sources_device(b, col, S, torch, sources=srcs)
         args = (b.tau0, dv(b.k_master), dv(b.tau), dv(b.w_tau), S, dv(b.w_lnk), dv(b.Pk))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -429,9 +431,11 @@ def fp64_solve(ctx, draws, torch):
 
 def run_emulator(args):
     """C5: emulator trained on batch-solver spectra (l = 2..5000, 8000 master k, 3000 tau);
-    held-out error judged by the FP64 plain path; inference on a batch of 4096 new parameter
-    sets with the fallback: the models the ensemble estimate flags above 1e-3 are re-solved by
-    the batched solver and merged (emu_merge), and the line's value is that end to end."""
+    held-out error judged by the FP64 plain path, which also calibrates the ensemble's error
+    estimate per spectrum; inference on a batch of 4096 new parameter sets with the fallback
+    spectrum by spectrum: the spectra whose calibrated estimate is above 1e-3 are re-solved by
+    the batched solver (the temperature source alone when TT is the only one) and merged, and
+    the line's value is that end to end."""
     import tempfile
     import torch
     from paper_2509_25110_amd import inputs, los
@@ -466,6 +470,13 @@ def run_emulator(args):
     per_spec = {nm: float(np.median(np.max(rel[:, i], axis=1)))
                 for i, nm in enumerate(("TT", "EE", "TE", "PP"))}
     progress("held-out (%d, FP64 judge): median error %.2e" % (len(te), np.median(true_err)))
+    # calibration of the ensemble spread, spectrum by spectrum: the largest ratio of true error
+    # (FP64 judge) to spread over the held-out models, with a 1.5 margin; the fallback below
+    # flags a spectrum when spread x calibration > 1e-3
+    _, e4h, _ = emu.emu_infer_spectra(dv(pte), threshold=thr)
+    e4h = e4h.cpu().numpy().astype(np.float64)
+    true4 = np.max(rel, axis=2)                                   # [held-out, 4]
+    calib = 1.5 * np.max(true4 / np.maximum(e4h, 1e-30), axis=0)
     # end to end on 4096 new parameter sets: emulate, re-solve the flagged ones, merge
     n = 4096
     new = inputs.draw_models(n, seed=3, **pin)
@@ -481,34 +492,51 @@ def run_emulator(args):
     end.record()
     torch.cuda.synchronize()
     infer_ms = start.elapsed_time(end) / K
+    # fallback spectrum by spectrum: a model whose EE, TE or PP misses the threshold is
+    # re-solved in full; one whose TT alone misses it, for the temperature source only
     t0 = time.perf_counter()
-    cl, err4, flag4 = emu.emu_infer(P, cl=cl_buf, threshold=thr)
-    rows = np.nonzero(flag4.cpu().numpy())[0]
+    cl, err4, flag4 = emu.emu_infer_spectra(P, cl=cl_buf, threshold=thr)
+    f4 = err4.cpu().numpy().astype(np.float64) * calib[None, :] > thr
+    full = np.nonzero(f4[:, 1:].any(axis=1))[0]
+    tt = np.setdiff1d(np.nonzero(f4[:, 0])[0], full)
     t_emu = time.perf_counter() - t0
-    t_fb, merged = 0.0, 0
-    if rows.size:
-        # the tuner's choice for this shape is in the context's cache from the training solves
-        _, cfb, t_fb = solve_models(ctx, [new[i] for i in rows], 2, torch, timed="plan+solve")
+    t_fb = 0.0
+    # the tuner's choice for these shapes is in the context's cache after the first plan
+    if full.size:
+        _, cfb, dt = solve_models(ctx, [new[i] for i in full], 2, torch, timed="plan+solve")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        emu.emu_merge(rows, cfb, cl, err=err4, flag=flag4)
+        emu.emu_merge(full, cfb, cl)
         torch.cuda.synchronize()
-        t_fb += time.perf_counter() - t1
-        merged = int(rows.size)
+        t_fb += dt + time.perf_counter() - t1
         del cfb
-    assert not bool(flag4.any().item())
+    if tt.size:
+        _, ctt, dt = solve_models(ctx, [new[i] for i in tt], 2, torch, timed="plan+solve",
+                                  tt_only=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        emu.emu_merge_spectrum(0, tt, ctt.reshape(tt.size, nl).contiguous(), cl, err4=err4,
+                               flag4=flag4)
+        torch.cuda.synchronize()
+        t_fb += dt + time.perf_counter() - t1
+        del ctt
+    resolved = np.zeros_like(f4)
+    resolved[full] = True
+    resolved[tt, 0] = True
+    assert np.all(resolved >= f4)
     effective = n / (t_emu + t_fb)
     # the same 4096 models solved by the batched solver alone (plan + solve): the time the
-    # emulator competes with, and the reference for the rows it kept
+    # emulator competes with, and the reference for the spectra it kept
     _, call, t_all = solve_models(ctx, new, 2, torch, timed="plan+solve")
     got, want = cl.cpu().numpy(), call.cpu().numpy()
     del call
-    keep = np.setdiff1d(np.arange(n), rows)
     kept_err = None
-    if keep.size:
-        sc = np.abs(want[keep]).copy()
-        sc[:, 2] = np.sqrt(want[keep][:, 0] * want[keep][:, 1])
-        kept_err = np.max(np.abs(got[keep] - want[keep]) / sc, axis=(1, 2))
+    if (~resolved).any():
+        sc = np.abs(want).copy()
+        sc[:, 2] = np.sqrt(want[:, 0] * want[:, 1])
+        rel = np.max(np.abs(got - want) / sc, axis=2)       # [n, 4]
+        kept_err = {name: rel[~resolved[:, i], i] for i, name in enumerate(("TT", "EE", "TE", "PP"))
+                    if (~resolved[:, i]).any()}
     emu_rate = n / (infer_ms * 1e-3)
     fp64_rate = len(te) / t64
     flops = n * 2.0 * (emu.nparams + 4 * 96 * nl) * emu.members
@@ -523,8 +551,9 @@ def run_emulator(args):
         "config": {"workload": "C5: emulator of TT/EE/TE/PP over l=2..5000 (8000 master k, 3000 "
                                "tau), 4 x MLP 5-512x4-384 GELU, PCA 96 per spectrum, %d training "
                                "spectra from the bf16x3 batched solver; one step = 4096 new "
-                               "parameter sets emulated, the flagged ones (estimate > 1e-3) "
-                               "re-solved by the batched solver (plan + solve, sources resident) "
+                               "parameter sets emulated, every spectrum whose estimate is above "
+                               "1e-3 re-solved by the batched solver (the temperature source "
+                               "alone when TT is the only one; plan + solve, sources resident) "
                                "and merged" % len(tr),
                    "train_spectra": len(tr), "heldout_spectra": len(te), "epochs": args.emu_epochs,
                    "parallelism": "single GPU"},
@@ -533,13 +562,19 @@ def run_emulator(args):
                      "traffic": None, "kernel": "emu_infer (4 members: MLP + reconstruction)",
                      "kernel_ms": infer_ms,
                      "work": "4096 x 4 members x 2 x (MLP params + 4 x 96 x %d)" % nl},
-        "fallback_threshold": thr, "fallback_models": merged,
-        "fallback_fraction": merged / n, "fallback_s": t_fb, "emulate_s": t_emu,
+        "fallback_threshold": thr,
+        "estimate_calibration": {nm: float(calib[i])
+                                 for i, nm in enumerate(("TT", "EE", "TE", "PP"))},
+        "fallback_models": int(resolved.any(axis=1).sum()),
+        "fallback_fraction": float(resolved.any(axis=1).mean()),
+        "fallback_full_models": int(full.size), "fallback_tt_only_models": int(tt.size),
+        "fallback_spectra_fraction": float(resolved.mean()),
+        "fallback_s": t_fb, "emulate_s": t_emu,
         "batched_solver_alone_spectra_per_s": n / t_all,
         "gain_vs_batched_solver": t_all / (t_emu + t_fb),
-        "kept_models_err_vs_batched_solver": None if kept_err is None else {
-            "median": float(np.median(kept_err)), "max": float(np.max(kept_err)),
-            "above_threshold": int(np.sum(kept_err > thr))},
+        "kept_spectra_err_vs_batched_solver": None if kept_err is None else {
+            k: {"count": int(v.size), "median": float(np.median(v)), "max": float(np.max(v)),
+                "above_threshold": int(np.sum(v > thr))} for k, v in kept_err.items()},
         "emulator_only_spectra_per_s": emu_rate,
         "fp64_plain_path_spectra_per_s": fp64_rate,
         "speedup_vs_fp64_plain_path": effective / fp64_rate,
@@ -575,8 +610,8 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle sample: every n-th k row (default 1 for C2, T2 and the C4 model, "
                          "4 for C3)")
-    ap.add_argument("--emu-train", type=int, default=4096, help="C5: training spectra")
-    ap.add_argument("--emu-epochs", type=int, default=300, help="C5: training epochs")
+    ap.add_argument("--emu-train", type=int, default=100000, help="C5: training spectra")
+    ap.add_argument("--emu-epochs", type=int, default=100, help="C5: training epochs")
     ap.add_argument("--emu-heldout", type=int, default=32,
                     help="C5: held-out models judged by the FP64 plain path")
     ap.add_argument("--emu-save", default="", help="C5: write the trained emulator to this file")

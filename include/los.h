@@ -322,7 +322,7 @@ int los_interp_sources(los_ctx *ctx, int32_t nsrc, int64_t nkc, int64_t ntau, co
  * LOS_BATCH_FUSED=0 at plan creation selects whole FP32 tables instead.
  *
  * los_batch_create (host arrays; allocates the plan's device tables and a
- * workspace of at most LOS_BATCH_MIB MiB (default 32768) of seeds plus
+ * workspace of at most LOS_BATCH_MIB MiB (default 8192) of seeds plus
  * products -- with LOS_BATCH_FUSED=0, LOS_JTAB_MIB MiB (default 4096) of
  * Bessel tables plus one chunk of products): lmax[nmodels] in [2, 16000]; koff[nmodels+1] with koff[0] = 0
  * and koff[m+1] > koff[m]; k_index[koff[nmodels]] in [0, nk_master);
@@ -416,6 +416,10 @@ void los_batch_destroy(los_batch *plan);
  *   need_fallback[n] uint8): cl = member mean of the reconstructed spectra;
  *   err = max over spectra, l and members of |C_e - C_mean| / scale (scale
  *   |C_mean|, for TE sqrt(C_TT C_EE)); need_fallback = !(err <= threshold).
+ * emu_infer_spectra: the same cl, with the estimate per spectrum instead:
+ *   err4[n][4] (TT, EE, TE, PP: max over l and members), need4[n][4] =
+ *   !(err4 <= threshold), so that a caller re-solves only the spectra that
+ *   miss the threshold; max over the four of err4[r] is emu_infer's err[r].
  * emu_forward / emu_loss_grad (device, float): one member's network output
  *   out[n][4 ncomp], and the loss (device, 1 float) with its gradient
  *   (device, nparams floats).
@@ -448,6 +452,8 @@ int emu_train(los_emu *emu, const double *params, const double *lo, const double
               float *loss_hist, void *stream);
 int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *err,
               uint8_t *need_fallback, double threshold, void *stream);
+int emu_infer_spectra(los_emu *emu, const double *params, int64_t n, double *cl, float *err4,
+                      uint8_t *need4, double threshold, void *stream);
 
 /*
  * Fallback merge: the rows of an emu_infer result that the caller re-solved
@@ -461,6 +467,21 @@ int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *
  */
 int emu_merge(los_emu *emu, const int64_t *rows, int64_t nf, const double *cl_solved, double *cl,
               int64_t n, float *err, uint8_t *need_fallback, void *stream);
+
+/*
+ * One-spectrum fallback merge (after emu_infer_spectra): spectrum s of the
+ * rows the caller re-solved replaces the emulator's, on `stream`:
+ *   cl[rows[i]][s][l] = cl_solved[i][l]   (l < nl), i < nf,
+ *   err4[rows[i]][s] = 0, need4[rows[i]][s] = 0   (err4, need4 may be NULL).
+ * For example a solve of the temperature source alone (los_batch_create with
+ * pairs {0, 0}) gives cl_solved[nf][1][nl] for s = 0 (TT).  rows: HOST, nf
+ * distinct indices in [0, n); cl_solved device doubles [nf][nl]; cl as in
+ * emu_infer.  nf == 0 is a no-op.  Errors: LOS_ERR_INVALID for s outside
+ * 0..3 or bad or repeated rows.
+ */
+int emu_merge_spectrum(los_emu *emu, int32_t spectrum, const int64_t *rows, int64_t nf,
+                       const double *cl_solved, double *cl, int64_t n, float *err4,
+                       uint8_t *need4, void *stream);
 
 /*
  * Checkpoints.  emu_save waits for `stream` (the stream of the emulator's last

@@ -544,11 +544,12 @@ int emu_train(los_emu *emu, const double *params, const double *lo, const double
   return ok();
 }
 
-int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *err,
-              uint8_t *need_fallback, double threshold, void *stream) {
-  if (!emu || !params || !cl || !err || !need_fallback || n < 1)
-    return fail(LOS_ERR_INVALID, "emu_infer: bad argument");
-  if (!emu->has_pca) return fail(LOS_ERR_INVALID, "emu_infer: emulator is not trained");
+// Inference shared by emu_infer (per-model estimates) and emu_infer_spectra
+// (per-spectrum estimates): any of err, need, err4, need4 may be NULL.
+static int infer(los_emu *emu, const char *who, const double *params, int64_t n, double *cl,
+                 float *err, uint8_t *need, float *err4, uint8_t *need4, double threshold,
+                 void *stream) {
+  if (!emu->has_pca) return fail(LOS_ERR_INVALID, "%s: emulator is not trained", who);
   hipStream_t s = (hipStream_t)stream;
   los_emu *m = emu;
   const int64_t nl = m->nl;
@@ -556,7 +557,7 @@ int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *
   if (rc == LOS_OK) rc = m->zt.reserve(sizeof(float) * (size_t)n * m->nout);
   if (rc == LOS_OK) rc = m->yall.reserve(sizeof(float) * (size_t)m->members * n * 4 * nl);
   if (rc == LOS_OK) rc = m->cz.reserve(sizeof(float) * (size_t)n * std::max(m->ncomp, m->np));
-  if (rc == LOS_OK) rc = m->errb.reserve(sizeof(unsigned int) * (size_t)n);
+  if (rc == LOS_OK) rc = m->errb.reserve(sizeof(unsigned int) * 4 * (size_t)n);
   if (rc != LOS_OK) return rc;
   HIPCHK(E::scale_params(params, n, m->np, m->lo.as<double>(), m->hi.as<double>(),
                          m->ut.as<float>(), s),
@@ -584,10 +585,26 @@ int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *
     }
   }
   HIPCHK(E::ensemble(m->yall.as<float>(), m->members, n, (int)nl, m->tscale.as<double>(), cl,
-                     m->errb.as<unsigned int>(), (float)threshold, err, need_fallback, s),
+                     m->errb.as<unsigned int>(), (float)threshold, err, need, err4, need4, s),
          "emu_infer: ensemble");
-  rc = los::check_result("emu_infer", cl, n * 4 * nl, false, s);
+  rc = los::check_result(who, cl, n * 4 * nl, false, s);
   return rc == LOS_OK ? ok() : rc;
+}
+
+int emu_infer(los_emu *emu, const double *params, int64_t n, double *cl, float *err,
+              uint8_t *need_fallback, double threshold, void *stream) {
+  if (!emu || !params || !cl || !err || !need_fallback || n < 1)
+    return fail(LOS_ERR_INVALID, "emu_infer: bad argument");
+  return infer(emu, "emu_infer", params, n, cl, err, need_fallback, nullptr, nullptr, threshold,
+               stream);
+}
+
+int emu_infer_spectra(los_emu *emu, const double *params, int64_t n, double *cl, float *err4,
+                      uint8_t *need4, double threshold, void *stream) {
+  if (!emu || !params || !cl || !err4 || !need4 || n < 1)
+    return fail(LOS_ERR_INVALID, "emu_infer_spectra: bad argument");
+  return infer(emu, "emu_infer_spectra", params, n, cl, nullptr, nullptr, err4, need4, threshold,
+               stream);
 }
 
 }  // extern "C"
@@ -763,6 +780,36 @@ int emu_merge(los_emu *emu, const int64_t *rows, int64_t nf, const double *cl_so
   HIPCHK(E::merge_rows(emu->rows.as<int64_t>(), nf, cl_solved, 4 * (int64_t)emu->nl, cl, err,
                        need_fallback, s),
          "emu_merge: launch");
+  return ok();
+}
+
+int emu_merge_spectrum(los_emu *emu, int32_t spectrum, const int64_t *rows, int64_t nf,
+                       const double *cl_solved, double *cl, int64_t n, float *err4,
+                       uint8_t *need4, void *stream) {
+  if (!emu || nf < 0 || n < 1 || spectrum < 0 || spectrum > 3)
+    return fail(LOS_ERR_INVALID, "emu_merge_spectrum: bad argument");
+  if (nf == 0) return ok();
+  if (!rows || !cl_solved || !cl) return fail(LOS_ERR_INVALID, "emu_merge_spectrum: NULL array");
+  if (nf > n)
+    return fail(LOS_ERR_INVALID, "emu_merge_spectrum: nf = %lld > n = %lld", (long long)nf,
+                (long long)n);
+  std::vector<char> seen((size_t)n, 0);
+  for (int64_t i = 0; i < nf; ++i) {
+    if (rows[i] < 0 || rows[i] >= n)
+      return fail(LOS_ERR_INVALID, "emu_merge_spectrum: rows[%lld] = %lld out of [0, %lld)",
+                  (long long)i, (long long)rows[i], (long long)n);
+    if (seen[(size_t)rows[i]]++)
+      return fail(LOS_ERR_INVALID, "emu_merge_spectrum: row %lld given twice",
+                  (long long)rows[i]);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = emu->rows.reserve(sizeof(int64_t) * (size_t)nf);
+  if (rc != LOS_OK) return rc;
+  HIPCHK(hipMemcpyAsync(emu->rows.p, rows, sizeof(int64_t) * (size_t)nf, hipMemcpyHostToDevice, s),
+         "emu_merge_spectrum: rows");
+  HIPCHK(E::merge_spectrum(emu->rows.as<int64_t>(), nf, cl_solved, emu->nl, spectrum, cl, err4,
+                           need4, s),
+         "emu_merge_spectrum: launch");
   return ok();
 }
 

@@ -62,13 +62,18 @@ hipError_t whiten(const double *c, int64_t n, int ncomp, int s_idx, int nout, do
                   float *z, hipStream_t s);
 hipError_t unwhiten(const float *out, int64_t n, int ncomp, int s_idx, int nout,
                     const double *sigma, float *cz, hipStream_t s);
+// Member mean into cl and the error estimates: per row (err, flag) and / or
+// per (row, spectrum) (err4, flag4), any of them NULL; err_bits has 4 n words.
 hipError_t ensemble(const float *y, int members, int64_t n, int nl, const double *t, double *cl,
                     unsigned int *err_bits, float thr, float *err, unsigned char *flag,
-                    hipStream_t s);
+                    float *err4, unsigned char *flag4, hipStream_t s);
 // cl[rows[i]][*] = src[i][*] (row_len values each), err[rows[i]] = 0, flag[rows[i]] = 0
 // (err, flag may be NULL); rows in [0, n) and distinct (checked by the caller).
 hipError_t merge_rows(const int64_t *rows, int64_t nf, const double *src, int64_t row_len,
                       double *cl, float *err, unsigned char *flag, hipStream_t s);
+// cl[rows[i]][spec][*] = src[i][*] (nl values each), err4 / flag4 of (rows[i], spec) = 0.
+hipError_t merge_spectrum(const int64_t *rows, int64_t nf, const double *src, int nl, int spec,
+                          double *cl, float *err4, unsigned char *flag4, hipStream_t s);
 
 }  // namespace emu
 }  // namespace los

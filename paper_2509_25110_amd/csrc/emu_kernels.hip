@@ -402,6 +402,9 @@ __global__ void unwhiten_kernel(const float *out, int64_t n, int ncomp, int s, i
 // (r, l): writes cl[r][s][l] (mean over members) for the 4 spectra and folds
 // the largest scaled deviation into err[r] (float bits, atomic max of
 // non-negative values: independent of order).
+// Member mean of every C_l and, per (row, spectrum), the largest member
+// deviation relative to the spectrum's scale (err_bits[r][4], float bits,
+// order-independent atomicMax).
 __global__ void ensemble_kernel(const float *y, int members, int64_t n, int nl, const double *t,
                                 double *cl, unsigned int *err_bits) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -419,24 +422,31 @@ __global__ void ensemble_kernel(const float *y, int members, int64_t n, int nl, 
     cl[(r * 4 + s) * nl + l] = mean[s];
   }
   double scale[4] = {fabs(mean[0]), fabs(mean[1]), sqrt(mean[0] * mean[1]), fabs(mean[3])};
-  double dev = 0.0;
+  double dev[4] = {0.0, 0.0, 0.0, 0.0};
   for (int e = 0; e < members; ++e)
     for (int s = 0; s < 4; ++s) {
       const double v = (double)y[(((int64_t)e * n + r) * 4 + s) * nl + l];
       const double c = s == 2 ? t[l] * sinh(v) : exp(v);
-      dev = fmax(dev, fabs(c - mean[s]) / scale[s]);
+      dev[s] = fmax(dev[s], fabs(c - mean[s]) / scale[s]);
     }
-  const float d = (float)dev;
-  atomicMax(err_bits + r, __float_as_uint(d));
+  for (int s = 0; s < 4; ++s) atomicMax(err_bits + r * 4 + s, __float_as_uint((float)dev[s]));
 }
 
+// Per row (err, flag: the largest of its four spectra) and / or per
+// (row, spectrum) (err4, flag4); any of the four may be NULL.
 __global__ void flag_kernel(const unsigned int *err_bits, int64_t n, float thr, float *err,
-                            unsigned char *flag) {
+                            unsigned char *flag, float *err4, unsigned char *flag4) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= n) return;
-  const float e = __uint_as_float(err_bits[r]);
-  err[r] = e;
-  flag[r] = !(e <= thr);
+  float emax = 0.f;
+  for (int s = 0; s < 4; ++s) {
+    const float e = __uint_as_float(err_bits[r * 4 + s]);
+    emax = fmaxf(emax, e);
+    if (err4) err4[r * 4 + s] = e;
+    if (flag4) flag4[r * 4 + s] = !(e <= thr);
+  }
+  if (err) err[r] = emax;
+  if (flag) flag[r] = !(emax <= thr);
 }
 
 __global__ void zero_u32_kernel(unsigned int *p, int64_t n) {
@@ -553,11 +563,12 @@ hipError_t unwhiten(const float *out, int64_t n, int ncomp, int s_idx, int nout,
 
 hipError_t ensemble(const float *y, int members, int64_t n, int nl, const double *t, double *cl,
                     unsigned int *err_bits, float thr, float *err, unsigned char *flag,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks(n)), dim3(256), 0, s, err_bits, n);
+                    float *err4, unsigned char *flag4, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks(4 * n)), dim3(256), 0, s, err_bits, 4 * n);
   hipLaunchKernelGGL(ensemble_kernel, dim3(blocks(n * nl)), dim3(256), 0, s, y, members, n, nl, t,
                      cl, err_bits);
-  hipLaunchKernelGGL(flag_kernel, dim3(blocks(n)), dim3(256), 0, s, err_bits, n, thr, err, flag);
+  hipLaunchKernelGGL(flag_kernel, dim3(blocks(n)), dim3(256), 0, s, err_bits, n, thr, err, flag,
+                     err4, flag4);
   return hipGetLastError();
 }
 
@@ -587,6 +598,35 @@ hipError_t merge_rows(const int64_t *rows, int64_t nf, const double *src, int64_
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(merge_rows_kernel, dim3((unsigned)b), dim3(256), 0, s, rows, nf, src, row_len,
                      cl, err, flag);
+  return hipGetLastError();
+}
+
+// One spectrum of the fallback rows: cl[rows[i]][spec][l] = src[i][l] for
+// l < nl; err4 / flag4 of (rows[i], spec) become 0 (both optional).
+__global__ __launch_bounds__(256) void merge_spectrum_kernel(const int64_t *rows, int64_t nf,
+                                                             const double *src, int nl, int spec,
+                                                             double *cl, float *err4,
+                                                             unsigned char *flag4) {
+  const int64_t total = nf * nl;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / nl, l = t - i * nl;
+    const int64_t r = rows[i];
+    cl[(r * 4 + spec) * nl + l] = src[t];
+    if (l == 0) {
+      if (err4) err4[r * 4 + spec] = 0.f;
+      if (flag4) flag4[r * 4 + spec] = 0;
+    }
+  }
+}
+
+hipError_t merge_spectrum(const int64_t *rows, int64_t nf, const double *src, int nl, int spec,
+                          double *cl, float *err4, unsigned char *flag4, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  int64_t b = (nf * nl + 255) / 256;
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(merge_spectrum_kernel, dim3((unsigned)b), dim3(256), 0, s, rows, nf, src, nl,
+                     spec, cl, err4, flag4);
   return hipGetLastError();
 }
 

@@ -341,10 +341,13 @@ def batch_sources_host(b: BatchInputs, col: np.ndarray, ncols: int) -> np.ndarra
     return S
 
 
-def batch_sources_device(b: BatchInputs, col: np.ndarray, S_packed, torch) -> None:
+def batch_sources_device(b: BatchInputs, col: np.ndarray, S_packed, torch,
+                         sources=(0, 1, 2)) -> None:
     """The same values as batch_sources_host, generated model by model on the device into the
     float32 tensor S_packed[ncols, ntau] (the full 256-model batch does not fit host memory
-    comfortably).  Same formulas as `sources`, evaluated by torch in float64."""
+    comfortably).  Same formulas as `sources`, evaluated by torch in float64.  `sources` lists
+    the source planes of the plan in order (0 T, 1 E, 2 lensing): (0,) fills a plan made for
+    the temperature source alone (pairs [(0, 0)])."""
     dev = S_packed.device
     tau = torch.from_numpy(b.tau).to(dev)
     lens = torch.from_numpy(lensing_kernel(b.tau)).to(dev)
@@ -354,9 +357,14 @@ def batch_sources_device(b: BatchInputs, col: np.ndarray, S_packed, torch) -> No
         k = torch.from_numpy(b.k_master[b.k_index[lo:hi]]).to(dev)[:, None]
         g = torch.exp(-((tau - d.tau_star) ** 2) / (2.0 * d.width * d.width))[None, :]
         rows = torch.from_numpy(col[lo:hi]).to(dev)
-        S_packed[rows] = (g * (1.0 + 0.3 * torch.cos(150.0 * k)) + d.a_isw * late[None, :]).float()
-        S_packed[rows + 1] = (0.5 * k * k * g).float()
-        S_packed[rows + 2] = lens[None, :].expand(hi - lo, -1).float()
+        for plane, src in enumerate(sources):
+            if src == 0:
+                v = g * (1.0 + 0.3 * torch.cos(150.0 * k)) + d.a_isw * late[None, :]
+            elif src == 1:
+                v = 0.5 * k * k * g
+            else:
+                v = lens[None, :].expand(hi - lo, -1)
+            S_packed[rows + plane] = v.float()
 
 
 def model_sources_device(wl: Workload, torch, device="cuda"):

@@ -41,7 +41,8 @@ EXPORTS = ("los_last_error", "los_version", "los_ctx_create", "los_ctx_destroy",
            "los_batch_destroy",
            "emu_create", "emu_destroy", "emu_nparams", "emu_get_params", "emu_set_params",
            "emu_get_pca", "emu_set_pca", "emu_forward", "emu_loss_grad", "emu_fit", "emu_train",
-           "emu_infer", "emu_merge", "emu_save", "emu_load")
+           "emu_infer", "emu_infer_spectra", "emu_merge", "emu_merge_spectrum", "emu_save",
+           "emu_load")
 
 
 class LosError(RuntimeError):
@@ -115,7 +116,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "emu_fit": [vp, i32, vp, vp, i64, i32, i32, dbl, vp, vp],
         "emu_train": [vp, vp, vp, vp, vp, i64, i32, i32, dbl, vp, vp],
         "emu_infer": [vp, vp, i64, vp, vp, vp, dbl, vp],
+        "emu_infer_spectra": [vp, vp, i64, vp, vp, vp, dbl, vp],
         "emu_merge": [vp, vp, i64, vp, vp, i64, vp, vp, vp],
+        "emu_merge_spectrum": [vp, i32, vp, i64, vp, vp, i64, vp, vp, vp],
         "emu_save": [vp, ctypes.c_char_p, vp],
         "emu_load": [vp, ctypes.c_char_p, ctypes.POINTER(vp)],
     }
@@ -469,6 +472,40 @@ class Emulator:
         _check(lib().emu_infer(self._h, _ptr(params), n, _ptr(cl), _ptr(err), _ptr(flag),
                                float(threshold), _stream(stream)))
         return cl, err, flag
+
+    def emu_infer_spectra(self, params: torch.Tensor, threshold: float = 1e-3, cl=None,
+                          stream=None):
+        """emu_infer with the error estimate and the fallback flag per spectrum:
+        (cl [n, 4, nl], err4 [n, 4] float32, flag4 [n, 4] uint8)."""
+        n = params.shape[0]
+        _need(params, torch.float64, n * self.nparam, "params")
+        if cl is None:
+            cl = torch.empty((n, 4, self.nl), dtype=torch.float64, device=params.device)
+        err4 = torch.empty((n, 4), dtype=torch.float32, device=params.device)
+        flag4 = torch.empty((n, 4), dtype=torch.uint8, device=params.device)
+        _check(lib().emu_infer_spectra(self._h, _ptr(params), n, _ptr(cl), _ptr(err4),
+                                       _ptr(flag4), float(threshold), _stream(stream)))
+        return cl, err4, flag4
+
+    def emu_merge_spectrum(self, spectrum: int, rows, cl_solved: torch.Tensor, cl: torch.Tensor,
+                           err4=None, flag4=None, stream=None):
+        """Replace spectrum `spectrum` (0 TT, 1 EE, 2 TE, 3 PP) of rows `rows` (host ints) by
+        re-solved values cl_solved [len(rows), nl] (float64, device); their err4 and flag4 of
+        that spectrum become 0."""
+        import numpy as np
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        n = cl.shape[0]
+        _need(cl, torch.float64, n * 4 * self.nl, "cl")
+        if r.size:
+            _need(cl_solved, torch.float64, r.size * self.nl, "cl_solved")
+        if err4 is not None:
+            _need(err4, torch.float32, 4 * n, "err4")
+        if flag4 is not None:
+            _need(flag4, torch.uint8, 4 * n, "flag4")
+        _check(lib().emu_merge_spectrum(self._h, int(spectrum), r.ctypes.data, r.size,
+                                        _ptr(cl_solved) if r.size else None, _ptr(cl), n,
+                                        _ptr(err4), _ptr(flag4), _stream(stream)))
+        return cl
 
     def emu_merge(self, rows, cl_solved: torch.Tensor, cl: torch.Tensor, err=None, flag=None,
                   stream=None):

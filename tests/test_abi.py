@@ -176,3 +176,21 @@ def test_lsample_validation(lib):
     assert ci(ctx, 2, ls, 3, p, 2, 9, p, None) == 1       # cl aliases cls
     assert ci(ctx, 0, ls, 3, p, 2, 9, d, None) == 1       # npairs = 0
     assert ci(None, 2, ls, 3, p, 2, 9, d, None) == 1
+
+
+def test_emu_spectra_validation(lib):
+    """The per-spectrum inference and merge reject bad arguments before any device work."""
+    p = ctypes.c_void_p(16)
+    assert lib.emu_infer_spectra(None, p, 4, p, p, p, 1e-3, None) == 1
+    rows = (ctypes.c_int64 * 2)(0, 1)
+    assert lib.emu_merge_spectrum(None, 0, rows, 2, p, p, 4, None, None, None) == 1
+    emu, _keep = _dummy_ctx()   # validation runs before the handle is used
+    assert lib.emu_merge_spectrum(emu, 4, rows, 2, p, p, 4, None, None, None) == 1  # no 5th spectrum
+    assert lib.emu_merge_spectrum(emu, -1, rows, 2, p, p, 4, None, None, None) == 1
+    assert lib.emu_merge_spectrum(emu, 0, rows, 3, p, p, 2, None, None, None) == 1  # nf > n
+    bad = (ctypes.c_int64 * 2)(1, 1)
+    assert lib.emu_merge_spectrum(emu, 0, bad, 2, p, p, 4, None, None, None) == 1
+    assert b"twice" in lib.los_last_error()
+    out = (ctypes.c_int64 * 2)(0, 7)
+    assert lib.emu_merge_spectrum(emu, 0, out, 2, p, p, 4, None, None, None) == 1
+    assert lib.emu_merge_spectrum(emu, 0, rows, 0, None, None, 4, None, None, None) == 0  # no-op

@@ -184,3 +184,164 @@ def test_emu_fallback_end_to_end(torch_dev, ctx):
              float(np.max(rel[keep])) if keep.size else float("nan"),
              per_emulated * 1e6, per_solve * 1e6, per_solve / per_emulated))
     emu.close()
+
+
+def test_emu_infer_spectra_matches_infer(torch_dev, ctx):
+    """Per-spectrum estimates: the same C_l bitwise, max over the four spectra of err4 is emu_infer's
+    err, and the flags follow the threshold spectrum by spectrum."""
+    torch = torch_dev
+    rng = np.random.default_rng(7)
+    emu = seeded_emulator(ctx, rng)
+    q = dev(torch, rng.uniform(-1, 1, size=(53, 5)))
+    _, e_probe, _ = emu.emu_infer_spectra(q, threshold=1.0)
+    thr = float(np.median(e_probe.cpu().numpy()))   # a float32 value: spectra on both sides
+    c0, e0, f0 = emu.emu_infer(q, threshold=thr)
+    c1, e4, f4 = emu.emu_infer_spectra(q, threshold=thr)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(c1.cpu().numpy(), c0.cpu().numpy())
+    e4, f4 = e4.cpu().numpy(), f4.cpu().numpy()
+    np.testing.assert_array_equal(e4.max(axis=1), e0.cpu().numpy())
+    np.testing.assert_array_equal(f4, (~(e4 <= thr)).astype(np.uint8))
+    np.testing.assert_array_equal(f4.max(axis=1), f0.cpu().numpy())
+    assert 0 < f4.sum() < f4.size, "the test wants some spectra on each side of the threshold"
+    emu.close()
+
+
+def test_emu_merge_spectrum(torch_dev, ctx):
+    from paper_2509_25110_amd import los
+    torch = torch_dev
+    rng = np.random.default_rng(9)
+    emu = seeded_emulator(ctx, rng)
+    n = 30
+    q = dev(torch, rng.uniform(-1, 1, size=(n, 5)))
+    c, e4, f4 = emu.emu_infer_spectra(q, threshold=0.0)   # every spectrum flagged
+    before = c.cpu().numpy().copy()
+    rows = np.array([29, 4, 11], dtype=np.int64)
+    solved = rng.standard_normal((rows.size, emu.nl))
+    emu.emu_merge_spectrum(2, rows, dev(torch, solved), c, err4=e4, flag4=f4)
+    torch.cuda.synchronize()
+    after, e, f = c.cpu().numpy(), e4.cpu().numpy(), f4.cpu().numpy()
+    np.testing.assert_array_equal(after[rows, 2], solved)
+    mask = np.ones_like(after, dtype=bool)
+    mask[rows, 2] = False
+    np.testing.assert_array_equal(after[mask], before[mask])
+    assert np.all(e[rows, 2] == 0) and np.all(f[rows, 2] == 0)
+    assert np.all(f[:, [0, 1, 3]] == 1) and np.sum(f[:, 2] == 0) == rows.size
+    for bad in ([0, 0], [-1], [n]):
+        with pytest.raises(los.LosError):
+            emu.emu_merge_spectrum(0, bad, dev(torch, np.zeros((len(bad), emu.nl))), c)
+    with pytest.raises(los.LosError):
+        emu.emu_merge_spectrum(4, [0], dev(torch, np.zeros((1, emu.nl))), c)
+    emu.close()
+
+
+def test_temperature_only_solve_matches_full(torch_dev, ctx):
+    """A plan for the temperature source alone (pairs [(0, 0)], one packed column per model and
+    k) gives bitwise the TT of the three-source plan: each column's products and the k-sum of a
+    pair do not depend on the other columns."""
+    torch = torch_dev
+    from paper_2509_25110_amd import inputs
+    draws = inputs.draw_models(40, seed=4, lmax_range=(150, 400), nk_range=(80, 200))
+    b = inputs.batch_inputs(draws, ntau=500, master_nk=200, master_kmax=0.08)
+    out = {}
+    for name, pairs, srcs in (("full", b.pairs, (0, 1, 2)), ("tt", np.array([[0, 0]]), (0,))):
+        for prec in (1, 2):
+            plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau,
+                                        pairs, prec=prec, nsrc=len(srcs))
+            col, ncols = plan.los_batch_columns()
+            S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
+            inputs.batch_sources_device(b, col, S, torch, sources=srcs)
+            cl = plan.los_batch_solve(b.tau0, dev(torch, b.k_master), dev(torch, b.tau),
+                                      dev(torch, b.w_tau), S, dev(torch, b.w_lnk),
+                                      dev(torch, b.Pk))
+            torch.cuda.synchronize()
+            out[name, prec] = cl.cpu().numpy()
+            plan.close()
+    for prec in (1, 2):
+        assert out["tt", prec].shape[1] == 1
+        np.testing.assert_array_equal(out["tt", prec][:, 0], out["full", prec][:, 0])
+
+
+def test_emu_per_spectrum_fallback_end_to_end(torch_dev, ctx):
+    """At the configured threshold (1e-3), spectrum by spectrum: models whose TT alone misses it
+    are re-solved for the temperature source only, models with another spectrum above it are
+    re-solved in full; every flagged spectrum then equals the batched solve's and every kept
+    one is the emulator's.  Prints the fraction of spectra re-solved and the time per spectrum
+    against solving everything."""
+    torch = torch_dev
+    from paper_2509_25110_amd import inputs, los
+
+    def solve(draws, tt_only=False):
+        b = inputs.batch_inputs(draws, ntau=400, master_nk=120, master_kmax=0.06)
+        pairs = np.array([[0, 0]]) if tt_only else b.pairs
+        srcs = (0,) if tt_only else (0, 1, 2)
+        plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, pairs,
+                                    prec=2, nsrc=len(srcs))
+        col, ncols = plan.los_batch_columns()
+        S = torch.empty((ncols, b.ntau), dtype=torch.float32, device="cuda")
+        inputs.batch_sources_device(b, col, S, torch, sources=srcs)
+        args = (b.tau0, dev(torch, b.k_master), dev(torch, b.tau), dev(torch, b.w_tau), S,
+                dev(torch, b.w_lnk), dev(torch, b.Pk))
+        plan.los_batch_solve(*args)                  # plan tuning and graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cl = plan.los_batch_solve(*args)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.close()
+        return cl, dt
+
+    def params(draws):
+        return np.array([[d.tau_star, d.width, d.a_isw, d.n_s, d.ln1e10As] for d in draws])
+
+    pin = dict(lmax_range=(200, 200), nk_range=(120, 120))
+    tr = inputs.draw_models(1024, seed=1, **pin)
+    te = inputs.draw_models(256, seed=2, **pin)
+    ctr, _ = solve(tr)
+    cte, solve_all_s = solve(te)
+    lo = np.array([260.0, 15.0, 0.0, 0.92, 2.9])
+    hi = np.array([300.0, 25.0, 0.2, 1.0, 3.2])
+    emu = los.Emulator(ctx, 5, ctr.shape[2], ncomp=24, width=128, depth=3, members=4, seed=5)
+    emu.emu_train(dev(torch, params(tr)), lo, hi, ctr, epochs=300, batch=128, lr=2e-3)
+    thr = 1e-3
+    P = dev(torch, params(te))
+    emu.emu_infer_spectra(P, threshold=thr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, e4, f4 = emu.emu_infer_spectra(P, threshold=thr)
+    f4h = f4.cpu().numpy().astype(bool)
+    emu_c = c.cpu().numpy()
+    t_emu = time.perf_counter() - t0
+    full = np.nonzero(f4h[:, 1:].any(axis=1))[0]
+    tt = np.setdiff1d(np.nonzero(f4h[:, 0])[0], full)
+    t_fb = 0.0
+    if full.size:
+        cf, dt = solve([te[i] for i in full])
+        t_fb += dt
+        emu.emu_merge(full, cf, c)
+    if tt.size:
+        ct, dt = solve([te[i] for i in tt], tt_only=True)
+        t_fb += dt
+        emu.emu_merge_spectrum(0, tt, ct.reshape(tt.size, -1).contiguous(), c, err4=e4, flag4=f4)
+    torch.cuda.synchronize()
+    got, ref = c.cpu().numpy(), cte.cpu().numpy()
+    resolved = np.zeros_like(f4h)
+    resolved[full] = True
+    resolved[tt, 0] = True
+    assert np.all(resolved >= f4h)                    # every flagged spectrum was re-solved
+    scale = np.abs(ref).copy()
+    scale[:, 2] = np.sqrt(ref[:, 0] * ref[:, 1])
+    rel = np.abs(got - ref) / scale                   # [n, 4, nl]
+    if resolved.any():
+        assert np.max(rel[resolved]) <= 1e-12, np.max(rel[resolved])
+    np.testing.assert_array_equal(got[~resolved], emu_c[~resolved])
+    per_emulated = (t_emu + t_fb) / len(te)
+    per_solve = solve_all_s / len(te)
+    kept = rel[~resolved]
+    print("per-spectrum fallback at %.0e: %d models in full, %d TT only (%.2f of the spectra "
+          "re-solved); kept spectra true error max %.2e; emulate + fall back %.2f us per model vs "
+          "solve %.2f us (gain %.2fx)"
+          % (thr, full.size, tt.size, resolved.mean(),
+             float(np.max(np.max(kept, axis=-1))) if kept.size else float("nan"),
+             per_emulated * 1e6, per_solve * 1e6, per_solve / per_emulated))
+    emu.close()
