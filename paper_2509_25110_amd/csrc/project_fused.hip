@@ -552,7 +552,11 @@ __global__ __launch_bounds__(64 * WR * WC) void fused_gemm_kernel(FusedArgs a, i
     // the next active chunk's inputs are in flight while the matrix cores run
     const int cn = next_chunk(ch.act0, ch.act1, c + 1);
     if (cn >= 0) load_chunk_in<TN, NT>(a, t, p, cn, lane, tid, in);
+    // FP32: the wave's products go ahead of the other workgroup's segment
+    // generation on the SIMD (1 % on C4; nothing for split-BF16x3)
+    if constexpr (PREC == 1) __builtin_amdgcn_s_setprio(1);
     mfma_chunk<PREC, TM, TN, MBW, NBW, WR>(acc, jlast, wr, wc, top_tr, g, r16, sm);
+    if constexpr (PREC == 1) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     c = cn;
   }
