@@ -21,34 +21,77 @@ __device__ inline float gelu_grad_f(float x) {
 
 // C(m, n) = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak],
 // B(k, n) = B[k sbk + n sbn], C row-major with leading dimension ldc.
-// Workgroup: 4 waves in a 2 x 2 arrangement, each wave 32 x 32 (2 x 2 MFMA
-// 16x16x4 blocks); rows and columns outside [M, N) and K beyond K read 0.
+// Workgroup: 64 x 64 of C, 4 waves in a 2 x 2 arrangement, each wave 32 x 32
+// (2 x 2 MFMA 16x16x4 blocks); rows and columns outside [M, N) and K beyond K
+// read 0.  K goes in tiles of 32: the workgroup stages the 64 x 32 slice of A
+// and the 32 x 64 slice of B in LDS, each loaded along whichever of its
+// strides is 1 (consecutive lanes, consecutive addresses), and loads the next
+// tile into registers while the matrix cores work on this one.  Every wave
+// issues its products in increasing k, 4 at a time.
 template <int EPI>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmF32 g) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int KT = 32, LD = 80;  // row pitch: the 4 k rows of a read hit distinct banks
+  __shared__ float As[KT][LD], Bs[KT][LD];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int64_t m0 = (int64_t)blockIdx.y * 64 + (w >> 1) * 32;
-  const int64_t n0 = (int64_t)blockIdx.x * 64 + (w & 1) * 32;
+  const int64_t mb = (int64_t)blockIdx.y * 64, nb = (int64_t)blockIdx.x * 64;
+  const int mw = (w >> 1) * 32, nw = (w & 1) * 32;
+  const int64_t m0 = mb + mw, n0 = nb + nw;
+  const bool a_k = g.sak == 1, b_n = g.sbn == 1;  // contiguous axis of each operand
+  // element it * 256 + tid of a tile: (row of A, k) and (k, column of B)
+  auto a_at = [&](int e, int &mm, int &kk) {
+    if (a_k) { kk = e & 31; mm = e >> 5; } else { mm = e & 63; kk = e >> 6; }
+  };
+  auto b_at = [&](int e, int &kk, int &nn) {
+    if (b_n) { nn = e & 63; kk = e >> 6; } else { kk = e & 31; nn = e >> 5; }
+  };
+  float ra[8], rb[8];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int e = it * 256 + tid;
+      int mm, kk, nn, kb;
+      a_at(e, mm, kk);
+      b_at(e, kb, nn);
+      const int64_t m = mb + mm, ka = k0 + kk, n = nb + nn, kB = k0 + kb;
+      ra[it] = (m < g.M && ka < g.K) ? g.A[m * g.sam + ka * g.sak] : 0.f;
+      rb[it] = (n < g.N && kB < g.K) ? g.B[kB * g.sbk + n * g.sbn] : 0.f;
+    }
+  };
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = 0; k0 < g.K; k0 += 4) {
-    const int64_t k = k0 + kq;
-    float a[2], b[2];
+  if (g.K > 0) load(0);
+  for (int64_t k0 = 0; k0 < g.K; k0 += KT) {
+    __syncthreads();  // the previous tile is consumed
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int64_t m = m0 + 16 * i + r16;
-      a[i] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : 0.f;
-      const int64_t n = n0 + 16 * i + r16;
-      b[i] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : 0.f;
+    for (int it = 0; it < 8; ++it) {
+      const int e = it * 256 + tid;
+      int mm, kk, nn, kb;
+      a_at(e, mm, kk);
+      b_at(e, kb, nn);
+      As[kk][mm] = ra[it];
+      Bs[kb][nn] = rb[it];
     }
+    __syncthreads();
+    if (k0 + KT < g.K) load(k0 + KT);
+    const int kn = g.K - k0 < KT ? (int)(g.K - k0) : KT;
+    for (int kk = 0; kk < kn; kk += 4) {
+      float a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[kk + kq][mw + 16 * i + r16];
+        b[i] = Bs[kk + kq][nw + 16 * i + r16];
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
