@@ -447,32 +447,52 @@ __global__ void unwhiten_kernel(const float *out, int64_t n, int ncomp, int s, i
 // non-negative values: independent of order).
 // Member mean of every C_l and, per (row, spectrum), the largest member
 // deviation relative to the spectrum's scale (err_bits[r][4], float bits,
-// order-independent atomicMax).
-__global__ void ensemble_kernel(const float *y, int members, int64_t n, int nl, const double *t,
-                                double *cl, unsigned int *err_bits) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n * nl) return;
-  const int64_t r = i / nl;
-  const int l = (int)(i % nl);
-  double mean[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int e = 0; e < members; ++e)
+// order-independent atomicMax).  Workgroup = one row r (blockIdx.x) and 256
+// multipoles (blockIdx.y): the deviations are reduced over the workgroup
+// first (max of the float bits, exact in any order), so each workgroup issues
+// four atomics instead of four per multipole on the same four addresses.
+__global__ __launch_bounds__(256) void ensemble_kernel(const float *y, int members, int64_t n,
+                                                       int nl, const double *t, double *cl,
+                                                       unsigned int *err_bits) {
+  __shared__ unsigned int red[4][4];
+  const int64_t r = blockIdx.x;
+  const int l = blockIdx.y * 256 + threadIdx.x;
+  unsigned int bits[4] = {0u, 0u, 0u, 0u};
+  if (l < nl) {
+    double mean[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < members; ++e)
+      for (int s = 0; s < 4; ++s) {
+        const double v = (double)y[(((int64_t)e * n + r) * 4 + s) * nl + l];
+        mean[s] += s == 2 ? t[l] * sinh(v) : exp(v);
+      }
     for (int s = 0; s < 4; ++s) {
-      const double v = (double)y[(((int64_t)e * n + r) * 4 + s) * nl + l];
-      mean[s] += s == 2 ? t[l] * sinh(v) : exp(v);
+      mean[s] /= members;
+      cl[(r * 4 + s) * nl + l] = mean[s];
     }
-  for (int s = 0; s < 4; ++s) {
-    mean[s] /= members;
-    cl[(r * 4 + s) * nl + l] = mean[s];
+    double scale[4] = {fabs(mean[0]), fabs(mean[1]), sqrt(mean[0] * mean[1]), fabs(mean[3])};
+    double dev[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < members; ++e)
+      for (int s = 0; s < 4; ++s) {
+        const double v = (double)y[(((int64_t)e * n + r) * 4 + s) * nl + l];
+        const double c = s == 2 ? t[l] * sinh(v) : exp(v);
+        dev[s] = fmax(dev[s], fabs(c - mean[s]) / scale[s]);
+      }
+    for (int s = 0; s < 4; ++s) bits[s] = __float_as_uint((float)dev[s]);
   }
-  double scale[4] = {fabs(mean[0]), fabs(mean[1]), sqrt(mean[0] * mean[1]), fabs(mean[3])};
-  double dev[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int e = 0; e < members; ++e)
-    for (int s = 0; s < 4; ++s) {
-      const double v = (double)y[(((int64_t)e * n + r) * 4 + s) * nl + l];
-      const double c = s == 2 ? t[l] * sinh(v) : exp(v);
-      dev[s] = fmax(dev[s], fabs(c - mean[s]) / scale[s]);
+  for (int s = 0; s < 4; ++s)
+    for (int o = 32; o >= 1; o >>= 1) {
+      const unsigned int u = __shfl_xor(bits[s], o, 64);
+      bits[s] = u > bits[s] ? u : bits[s];
     }
-  for (int s = 0; s < 4; ++s) atomicMax(err_bits + r * 4 + s, __float_as_uint((float)dev[s]));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int s = 0; s < 4; ++s) red[w][s] = bits[s];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned int m = 0u;
+    for (int v = 0; v < 4; ++v) m = red[v][threadIdx.x] > m ? red[v][threadIdx.x] : m;
+    atomicMax(err_bits + r * 4 + threadIdx.x, m);
+  }
 }
 
 // Per row (err, flag: the largest of its four spectra) and / or per
@@ -608,8 +628,10 @@ hipError_t ensemble(const float *y, int members, int64_t n, int nl, const double
                     unsigned int *err_bits, float thr, float *err, unsigned char *flag,
                     float *err4, unsigned char *flag4, hipStream_t s) {
   hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks(4 * n)), dim3(256), 0, s, err_bits, 4 * n);
-  hipLaunchKernelGGL(ensemble_kernel, dim3(blocks(n * nl)), dim3(256), 0, s, y, members, n, nl, t,
-                     cl, err_bits);
+  if (n > 0x7fffffff) return hipErrorInvalidValue;  // one workgroup row per model row
+  if (n > 0 && nl > 0)
+    hipLaunchKernelGGL(ensemble_kernel, dim3((unsigned)n, (unsigned)((nl + 255) / 256)), dim3(256), 0,
+                       s, y, members, n, nl, t, cl, err_bits);
   hipLaunchKernelGGL(flag_kernel, dim3(blocks(n)), dim3(256), 0, s, err_bits, n, thr, err, flag,
                      err4, flag4);
   return hipGetLastError();
