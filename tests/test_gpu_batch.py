@@ -94,6 +94,36 @@ def test_batch_small_vs_oracle(torch_dev, ctx, prec):
     plan.close()
 
 
+def test_batch_pair_table_any_order(torch_dev, ctx):
+    """Output pairs in any order, reversed, repeated and crossed (the k-sum accumulates per
+    ordered source pair and each output pair reads its own sum): every pair's C_l within the
+    bound of test_batch_small_vs_oracle against the oracle with the same pair table, and a
+    repeated pair bitwise equal to its first occurrence."""
+    b = small_batch(seed=17)
+    pairs = [(1, 0), (0, 0), (2, 1), (0, 1), (1, 0), (2, 2), (0, 2)]
+    plan = ctx.los_batch_create(b.lmax, b.koff, b.k_index, b.k_master.size, b.ntau, pairs,
+                                prec=1)
+    plan, S, cl = solve(torch_dev, ctx, b, 1, plan=plan)
+    assert cl.shape[1] == len(pairs)
+    col, _ = plan.los_batch_columns()
+    S32 = S.cpu().numpy()
+    for m in range(b.nmodels):
+        L = int(b.lmax[m])
+        lo, hi = int(b.koff[m]), int(b.koff[m + 1])
+        k = b.k_master[b.k_index[lo:hi]]
+        Sm = np.stack([S32[col[lo:hi] + s].astype(np.float64) for s in range(3)])
+        d, A = oracle.project(2, L, k, b.tau, b.tau0, b.w_tau, Sm, with_abs=True)
+        cref = oracle.cl(d, b.w_lnk[lo:hi], b.Pk[lo:hi], pairs)
+        CA = oracle.cl(A, b.w_lnk[lo:hi], b.Pk[lo:hi], pairs)
+        got = cl[m, :, :L - 1]
+        bound = np.maximum(1e-4 * np.abs(cref), 2.2 * eps_for(1, b.ntau) * CA)
+        worst = float(np.max(np.abs(got - cref) / bound))
+        assert worst <= 1.0, (m, worst)
+        np.testing.assert_array_equal(cl[m, 4], cl[m, 0])   # (1, 0) twice
+        assert np.all(cl[m, :, L - 1:] == 0.0), m
+    plan.close()
+
+
 def test_batch_graph_replays_match_eager(torch_dev, ctx, monkeypatch):
     """The captured graph, replayed several times with eager work and synchronisation in between,
     gives the eager launch sequence's result bitwise every time."""
